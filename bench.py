@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload (the force microbenchmark configuration): a Plummer sphere of
+N = 65,536 equal masses (seed 2002), softening 1e-4, Henon units.  One
+timed step runs the whole block-step hot path five times, once for each
+active-set size N_act in {1, 64, 1024, 8192, 65,536} (random subsets,
+seed 2003): the state is reset so that exactly that subset is due, then
+schedule -> predict all N sources -> evaluate a, da, d2a, phi of the active
+particles -> split-source reduction -> corrector + interpolation + new block
+step.  The last block has every particle active, which synchronizes the
+system; the step ends with the FP64 energy / angular momentum sums of the
+synchronized state.
+
+value = force interactions (N * N_act summed over the five blocks) per
+second of wall time over the timed steps, inputs resident in HBM.
+
+Also reported: the same for the all-FP64 path and the speedup; the energy
+error of both paths on the 1024-body Plummer run to t = 1 (eta = 0.45); the
+per-phase GPU time; the roofline of the dominant kernel (the evaluation
+kernel at N_act = N, timed with HIP events on its stream); and the CPU
+oracle timed on a bounded sample of the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G interactions/s (acc+jerk+snap), mixed vs FP64 at equal ΔE/E; % VALU peak"
+N_ACTS = (1, 64, 1024, 8192, 65536)
+# algorithmic flops per pair (FMA = 2, rsqrt = 4; the count of the method's
+# difference, distance, rsqrt, alpha/beta, A/J/S and accumulation terms)
+FLOPS_PER_PAIR = 83
+PAPER_FLOPS_PER_PAIR = 97      # the paper's convention (Table 2)
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
+# is switched off in this build, so the attainable FP32 vector rate equals
+# the FP64 vector rate.
+PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
+PEAK_FP32_DATASHEET = 157.3                          # counts packed FP32
+PEAK_FP64 = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Workload:
+    """The N-body state and the five prepared active-set schedules."""
+
+    def __init__(self, n, precision, autotune):
+        import numpy as np
+        import torch
+
+        import ics
+        from paper_1207_2367_amd import System
+        self.n = n
+        m, x, v = ics.plummer(n, 2002)
+        self.sys = System(m, x, v, 1e-4, precision=precision)
+        if autotune:
+            self.sys.autotune(150.0)
+        st = self.sys.get_state()
+        self.base = {k: st[k].clone() for k in ("x", "v", "a", "jk", "sn", "cr")}
+        self.t0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        self.dts = []
+        self.sizes = [min(k, n) for k in N_ACTS]
+        rng = np.random.default_rng(2003)
+        for na in self.sizes:
+            dt = np.full(n, 2.0 ** -4)
+            dt[rng.choice(n, na, replace=False)] = 2.0 ** -10
+            self.dts.append(torch.as_tensor(dt, device="cuda"))
+        self.pairs_per_step = float(sum(n * na for na in self.sizes))
+
+    def step(self):
+        s = self.sys
+        for dt in self.dts:
+            s.set_state(t=self.t0, dt=dt, **self.base)
+            na, tb = s.block_step(1.0 / 16)
+        return s.energy()
+
+    def run(self, steps, warmup, profile=False):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        if profile:
+            self.sys.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = self.sys.profile(False) if profile else None
+        return t1 - t0, prof
+
+
+def energy_error(precision):
+    """Delta E / E of the 1024-body Plummer sphere integrated to t = 1."""
+    import ics
+    from paper_1207_2367_amd import NBodyError, System
+    m, x, v = ics.plummer(1024, 1001)
+    s = System(m, x, v, 1e-4, precision=precision)
+    e0 = sum(s.energy()[:2])
+    try:
+        st = s.step(1.0)
+    except NBodyError as e:
+        return None, str(e)
+    e1 = sum(s.energy()[:2])
+    return (e1 - e0) / e0, st["block_steps"]
+
+
+def cpu_baseline(n, seconds):
+    """The oracle timed on this host's cores on a bounded sample of the same
+    step: one block step (schedule, predict all N, evaluate the sampled
+    active set, correct it) with a sampled active set sized for ~seconds."""
+    import numpy as np
+
+    import ics
+    import oracle
+    m, x, v = ics.plummer(n, 2002)
+    a = ics.plummer_mean_acc(x)
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+
+    def one(n_act):
+        it = oracle.Integrator(m, x, v, 1e-4)
+        dt = np.full(n, 2.0 ** -4)
+        dt[np.random.default_rng(2003).choice(n, n_act, replace=False)] = 2.0 ** -10
+        it.set_state(a=a, t=np.zeros(n), dt=dt)
+        t0 = time.perf_counter()
+        err, na, tb = it.block_step(1.0 / 16)
+        return time.perf_counter() - t0, na
+
+    dt_cal, _ = one(64)
+    rate = 64 * n / max(dt_cal, 1e-6)
+    n_act = int(min(n, max(64, seconds * rate / n)))
+    el, na = one(n_act)
+    return {"value": round(na * n / el / 1e9, 4), "unit": "G interactions/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one block step of the N={n} Plummer sphere with a random active set of "
+                      f"{na} particles (predict all N, evaluate {na} x {n} pairs, correct): "
+                      f"{el:.1f} s, FP64 C oracle, OpenMP over active particles"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has "
+              "no multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED
+    from paper_1207_2367_amd import nbody
+    if not os.path.exists(nbody.lib_path()):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    log(f"mixed: N={args.n}, warmup {args.warmup}, steps {args.steps}")
+    wl = Workload(args.n, PREC_MIXED, not args.no_autotune)
+    launches = {na: wl.sys.get_launch(na) for na in wl.sizes}
+    el, prof = wl.run(args.steps, args.warmup, profile=True)
+    value = wl.pairs_per_step * args.steps / el / 1e9
+    na_log, pr_log, ms_log = wl.sys.force_log()
+    log(f"mixed: {el / args.steps * 1e3:.3f} ms/step, {value:.2f} G interactions/s")
+
+    # dominant kernel: the evaluation at N_act = N
+    import numpy as np
+    sel = na_log == args.n
+    avg_ms = float(ms_log[sel].mean())
+    pairs = float(args.n) * args.n
+    achieved = FLOPS_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
+    per_nact = {}
+    for na in wl.sizes:
+        s = na_log == na
+        t = float(ms_log[s].mean())
+        per_nact[str(na)] = {"kernel_ms": round(t, 5),
+                             "G_interactions_per_s": round(na * args.n / (t * 1e-3) / 1e9, 3),
+                             "launch": {"lanes_per_i": launches[na][0], "waves": launches[na][1],
+                                        "split": launches[na][2]}}
+    phases = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if k != "pairs"}
+
+    log("fp64 path")
+    ks = args.fp64_steps or max(2, args.steps // 2)
+    wd = Workload(args.n, PREC_FP64, not args.no_autotune)
+    eld, profd = wd.run(ks, 1, profile=True)
+    value_f64 = wd.pairs_per_step * ks / eld / 1e9
+    na_d, _, ms_d = wd.sys.force_log()
+    avg_ms_d = float(ms_d[na_d == args.n].mean())
+    del wd
+
+    log("energy error, 1024-body Plummer to t = 1")
+    de_mixed, steps_m = energy_error(PREC_MIXED)
+    de_f64, steps_d = energy_error(PREC_FP64)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.n, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "G interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Plummer N={args.n} (seed 2002), eps=1e-4, Henon units; one step = "
+                        "block steps with N_act in {1, 64, 1024, 8192, 65536} (schedule, "
+                        "predict, evaluate, reduce, correct, new steps) + FP64 energy of the "
+                        "synchronized state",
+            "n": args.n, "n_act": list(wl.sizes), "precision": "mixed",
+        },
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED, 2),
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
+            "kernel": "evaluation (force) kernel, N_act = N",
+            "kernel_avg_ms": round(avg_ms, 5), "flops_per_pair": FLOPS_PER_PAIR,
+            "frac_vs_fp32_datasheet_157.3": round(achieved / PEAK_FP32_DATASHEET, 4),
+        },
+        "fp64_path": {
+            "value": round(value_f64, 3), "unit": "G interactions/s",
+            "kernel_ms_at_N": round(avg_ms_d, 5),
+            "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12, 3),
+            "frac_fp64_peak": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12 / PEAK_FP64, 4),
+        },
+        "speedup_mixed_vs_fp64": round(value / value_f64, 3),
+        "kernel_speedup_mixed_vs_fp64": round(avg_ms_d / avg_ms, 3),
+        "dE_over_E_plummer1024_t1": {"mixed": de_mixed, "fp64": de_f64,
+                                     "block_steps": [steps_m, steps_d]},
+        "paper_equiv_gflops": round(value * PAPER_FLOPS_PER_PAIR, 1),
+        "per_n_act": per_nact,
+        "phase_ms_per_step": phases,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,888 @@
+// C ABI of the library (declared in include/nbody.h): argument checks,
+// workspace layout, and the host sequence of kernels of each call.  All
+// arithmetic runs in the kernels of force.hip and integrate.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "nbody_internal.h"
+
+using namespace nb;
+
+struct nbody_ctx {
+    Ctx c;
+};
+
+namespace {
+
+constexpr int64_t ALIGN = 256;
+
+int64_t align_up(int64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_pow2(double x)
+{
+    if (!(x > 0.0) || !std::isfinite(x))
+        return false;
+    int e;
+    return std::frexp(x, &e) == 0.5;
+}
+
+bool config_ok(const nbody_config *cfg, int64_t n)
+{
+    if (!cfg)
+        return false;
+    if (!(cfg->eta > 0.0) || !std::isfinite(cfg->eta))
+        return false;
+    if (!(cfg->eta_init > 0.0) || !std::isfinite(cfg->eta_init))
+        return false;
+    if (!is_pow2(cfg->dt_min) || !is_pow2(cfg->dt_max) || cfg->dt_min > cfg->dt_max)
+        return false;
+    if (cfg->precision != NBODY_PREC_MIXED && cfg->precision != NBODY_PREC_FP64)
+        return false;
+    if (cfg->n_clusters > 1) {
+        const int64_t *o = cfg->cluster_offsets;
+        if (!o || o[0] != 0 || o[cfg->n_clusters] != n)
+            return false;
+        for (int32_t c = 0; c < cfg->n_clusters; ++c)
+            if (o[c + 1] <= o[c])
+                return false;
+    }
+    return true;
+}
+
+int32_t n_clusters(const nbody_config *cfg) { return cfg->n_clusters > 1 ? cfg->n_clusters : 1; }
+
+int64_t count_chunks(const std::vector<int64_t> &off)
+{
+    int64_t k = 0;
+    for (size_t c = 0; c + 1 < off.size(); ++c)
+        k += (off[c + 1] - off[c] + SCHED_CHUNK - 1) / SCHED_CHUNK;
+    return k;
+}
+
+int fail(Ctx &c, int code, const char *what)
+{
+    c.last_error = what;
+    return code;
+}
+
+int hip_fail(Ctx &c, hipError_t e, const char *where)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    c.last_error = buf;
+    return NBODY_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                  \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess)                              \
+            return hip_fail((ctx), e_, #call);             \
+    } while (0)
+
+// read the device error word; clear it; map it to a return code
+int take_err(Ctx &c)
+{
+    HIPCHK(c, hipMemcpyAsync(c.h_err, c.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    const uint32_t e = *c.h_err;
+    if (!e)
+        return NBODY_OK;
+    HIPCHK(c, hipMemsetAsync(c.d_err, 0, sizeof(uint32_t), c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    if (e & ERR_NONFINITE)
+        return fail(c, NBODY_ENONFINITE, "non-finite value in the state");
+    if (e & ERR_DTMIN)
+        return fail(c, NBODY_EDTMIN, "a particle needs a step below dt_min");
+    return fail(c, NBODY_EINVAL, "index list out of range / not ascending, or a particle is past the target time");
+}
+
+}  // namespace
+
+// Workspace layout: every array 256-byte aligned.  With base == nullptr
+// only the size is computed.
+int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
+{
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        char *p = base ? base + o : nullptr;
+        o += align_up(bytes);
+        return p;
+    };
+    const int64_t d = sizeof(double), f = sizeof(float);
+    const int64_t part_cap = std::max<int64_t>(2 * n, int64_t(1) << 20);
+    const int64_t n_chunks_max = n / SCHED_CHUNK + nc + 1;
+    State st{};
+    st.pos = (double *)take(3 * n * d);
+    st.vel = (double *)take(3 * n * d);
+    st.acc = (double *)take(3 * n * d);
+    st.jrk = (double *)take(3 * n * d);
+    st.snp = (double *)take(3 * n * d);
+    st.crk = (double *)take(3 * n * d);
+    st.t = (double *)take(n * d);
+    st.dt = (double *)take(n * d);
+    st.mass = (double *)take(n * d);
+    JRecMixed jm{};
+    JRecF64 jd{};
+    if (prec == NBODY_PREC_MIXED) {
+        jm.x = (double *)take(n * d);
+        jm.y = (double *)take(n * d);
+        jm.z = (double *)take(n * d);
+        float **fl[7] = {&jm.vx, &jm.vy, &jm.vz, &jm.ax, &jm.ay, &jm.az, &jm.m};
+        for (auto p : fl)
+            *p = (float *)take(n * f);
+    } else {
+        double **dl[10] = {&jd.x, &jd.y, &jd.z, &jd.vx, &jd.vy, &jd.vz, &jd.ax, &jd.ay, &jd.az, &jd.m};
+        for (auto p : dl)
+            *p = (double *)take(n * d);
+    }
+    double *part = (double *)take(10 * part_cap * d);
+    int32_t *act = (int32_t *)take(n * 4);
+    double *fnew = (double *)take(10 * n * d);
+    int64_t *d_off = (int64_t *)take((nc + 1) * 8);
+    int32_t *cl_of = nc > 1 ? (int32_t *)take(n * 4) : nullptr;
+    int32_t *ch_cl = (int32_t *)take(n_chunks_max * 4);
+    int64_t *ch_b = (int64_t *)take((n_chunks_max + 1) * 8);
+    uint64_t *tmin = (uint64_t *)take(nc * 8);
+    double *tblock = (double *)take(nc * d);
+    int32_t *ch_cnt = (int32_t *)take(n_chunks_max * 4);
+    int64_t *ch_pos = (int64_t *)take(n_chunks_max * 8);
+    int64_t *seg = (int64_t *)take((nc + 1) * 8);
+    int32_t *blk_cl = (int32_t *)take((n + nc + 1) * 4);
+    int64_t *blk_first = (int64_t *)take((nc + 1) * 8);
+    int64_t *info = (int64_t *)take(64 * 8);
+    uint32_t *err = (uint32_t *)take(4);
+    const int64_t red_cap = 5 * (n / 256 + 2) + 16;
+    double *red = (double *)take(red_cap * d);
+    double *phi = (double *)take(n * d);
+    if (c) {
+        c->st = st;
+        c->jm = jm;
+        c->jd = jd;
+        c->part = part;
+        c->part_cap = part_cap;
+        c->act = act;
+        c->fnew = fnew;
+        c->d_off = d_off;
+        c->d_cluster_of = cl_of;
+        c->d_chunk_cluster = ch_cl;
+        c->d_chunk_begin = ch_b;
+        c->d_tmin = tmin;
+        c->d_tblock = tblock;
+        c->d_chunk_cnt = ch_cnt;
+        c->d_chunk_pos = ch_pos;
+        c->d_seg = seg;
+        c->d_blk_cluster = blk_cl;
+        c->d_blk_first = blk_first;
+        c->d_info = info;
+        c->d_err = err;
+        c->d_red = red;
+        c->red_cap = red_cap;
+        c->d_phi = phi;
+    }
+    return o;
+}
+
+int nb::prof_begin(Ctx &c, int phase, int64_t n_act, double pairs)
+{
+    if (!c.prof)
+        return -1;
+    if (c.prof_pending.size() >= 4096 && prof_collect(c) != hipSuccess)
+        return -1;   // bounded event use on long runs
+    ProfRec r{};
+    r.phase = phase;
+    r.n_act = n_act;
+    r.pairs = pairs;
+    for (hipEvent_t *e : {&r.a, &r.b}) {
+        if (!c.prof_pool.empty()) {
+            *e = c.prof_pool.back();
+            c.prof_pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            return -1;
+        }
+    }
+    if (hipEventRecord(r.a, c.stream) != hipSuccess)
+        return -1;
+    c.prof_pending.push_back(r);
+    return (int)c.prof_pending.size() - 1;
+}
+
+void nb::prof_end(Ctx &c, int rec)
+{
+    if (rec < 0 || rec >= (int)c.prof_pending.size())
+        return;
+    (void)hipEventRecord(c.prof_pending[rec].b, c.stream);
+}
+
+hipError_t nb::prof_collect(Ctx &c)
+{
+    if (c.prof_pending.empty())
+        return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess)
+        return e;
+    for (ProfRec &r : c.prof_pending) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess)
+            return e;
+        c.prof_ms[r.phase] += ms;
+        c.prof_cnt[r.phase] += 1;
+        if (r.phase == PH_FORCE) {
+            c.prof_pairs += r.pairs;
+            c.flog_nact.push_back(r.n_act);
+            c.flog_pairs.push_back(r.pairs);
+            c.flog_ms.push_back(ms);
+        }
+        c.prof_pool.push_back(r.a);
+        c.prof_pool.push_back(r.b);
+    }
+    c.prof_pending.clear();
+    return hipSuccess;
+}
+
+namespace {
+
+int64_t max_cluster(const Ctx &c)
+{
+    int64_t m = 0;
+    for (size_t k = 0; k + 1 < c.off.size(); ++k)
+        m = std::max(m, c.off[k + 1] - c.off[k]);
+    return m;
+}
+
+// force of the active slots described by c.d_seg (and idx) into out
+int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, const ForceOut &out,
+              double pairs_hint = -1.0)
+{
+    Launch L = pick_launch(c, n_act_typ, max_cluster(c));
+    while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
+        L.split >>= 1;
+    const int64_t ib = iblock_size(L);
+    ForceWork w{};
+    w.idx = idx;
+    w.seg = c.d_seg;
+    w.off = c.d_off;
+    w.split = L.split;
+    w.nc = c.nc;
+    if (c.nc == 1) {
+        w.n_blocks = (n_act + ib - 1) / ib;
+    } else {
+        const int64_t cap = n_act / ib + c.nc + 1;
+        HIPCHK(c, launch_blocks(c, ib, cap, c.stream));
+        w.blk_cluster = c.d_blk_cluster;
+        w.blk_first = c.d_blk_first;
+        w.n_blocks = cap;
+    }
+    const size_t before = c.prof_pending.size();
+    HIPCHK(c, launch_force(c, w, L, out, n_act, c.stream));
+    // interactions of this launch, for the profile: n_act * N with one
+    // cluster; with several, the block step fills it from the schedule
+    for (size_t r = before; r < c.prof_pending.size(); ++r)
+        if (c.prof_pending[r].phase == PH_FORCE)
+            c.prof_pending[r].pairs = pairs_hint >= 0 ? pairs_hint : (double)n_act * (double)c.n;
+    return NBODY_OK;
+}
+
+// one block step; fills n_act / t_block and adds to stats
+int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
+               nbody_step_stats *stats)
+{
+    int rec = prof_begin(c, PH_SCHED);
+    HIPCHK(c, launch_schedule(c, t_target, c.stream));
+    prof_end(c, rec);
+    HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    const int64_t n_act = c.h_info[0];
+    double tb;
+    std::memcpy(&tb, &c.h_info[1], 8);
+    if (c.h_info[3] != 0)
+        return take_err(c);
+    *n_act_out = n_act;
+    *t_block_out = tb;
+    if (n_act == 0)
+        return NBODY_OK;
+    rec = prof_begin(c, PH_PREDICT);
+    HIPCHK(c, launch_pack(c, c.d_tblock, 0, c.d_cluster_of, c.stream));
+    prof_end(c, rec);
+    ForceOut out{};
+    out.vec[0] = c.fnew;
+    out.vec[1] = c.fnew + 3 * n_act;
+    out.vec[2] = c.fnew + 6 * n_act;
+    out.pot = nullptr;
+    out.sk = 1;
+    out.sd = n_act;
+    int64_t active_clusters = 0;
+    (void)active_clusters;
+    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / c.nc);
+    int rc = run_force(c, c.act, n_act, typ, out, (double)c.h_info[2]);
+    if (rc)
+        return rc;
+    rec = prof_begin(c, PH_CORRECT);
+    HIPCHK(c, launch_correct(c, n_act, c.act, t_target, out.vec[0], out.vec[1], out.vec[2], 1,
+                             n_act, c.stream));
+    prof_end(c, rec);
+    if (stats) {
+        stats->block_steps += 1;
+        stats->active_total += n_act;
+        stats->interactions += (double)c.h_info[2];
+    }
+    return NBODY_OK;
+}
+
+bool on_grid(double t, double dt_min)
+{
+    if (!(t >= 0.0) || !std::isfinite(t))
+        return false;
+    const double q = t / dt_min;
+    return q == std::floor(q);
+}
+
+}  // namespace
+
+extern "C" {
+
+void nbody_default_config(nbody_config *cfg)
+{
+    if (!cfg)
+        return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->eta = 0.45;
+    cfg->eta_init = 0.01;
+    cfg->dt_min = std::ldexp(1.0, -25);
+    cfg->dt_max = 1.0 / 16;
+    cfg->precision = NBODY_PREC_MIXED;
+    cfg->n_clusters = 1;
+}
+
+size_t nbody_workspace_bytes(int64_t n, const nbody_config *cfg)
+{
+    if (n <= 0 || n > (int64_t(1) << 31) - 1 || !config_ok(cfg, n))
+        return 0;
+    return (size_t)ws_layout(n, n_clusters(cfg), cfg->precision, nullptr, nullptr);
+}
+
+const char *nbody_strerror(int code)
+{
+    switch (code) {
+    case NBODY_OK: return "ok";
+    case NBODY_EINVAL: return "invalid argument";
+    case NBODY_EDEVICE: return "HIP runtime error";
+    case NBODY_ENONFINITE: return "non-finite value";
+    case NBODY_EDTMIN: return "time step below dt_min required";
+    case NBODY_ESTATE: return "invalid state for this call";
+    default: return "unknown error";
+    }
+}
+
+const char *nbody_last_error(const nbody_ctx *ctx)
+{
+    return ctx ? ctx->c.last_error.c_str() : "null context";
+}
+
+int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d_pos,
+               const double *d_vel, double eps, const nbody_config *cfg, void *d_workspace,
+               size_t ws_bytes)
+{
+    if (!out)
+        return NBODY_EINVAL;
+    *out = nullptr;
+    if (n <= 0 || n > (int64_t(1) << 31) - 1 || !d_mass || !d_pos || !d_vel || !d_workspace ||
+        !(eps >= 0.0) || !std::isfinite(eps) || !config_ok(cfg, n))
+        return NBODY_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) % ALIGN) != 0)
+        return NBODY_EINVAL;
+    const int32_t nc = n_clusters(cfg);
+    if ((int64_t)ws_bytes < ws_layout(n, nc, cfg->precision, nullptr, nullptr))
+        return NBODY_EINVAL;
+    nbody_ctx *h = new (std::nothrow) nbody_ctx;
+    if (!h)
+        return NBODY_EINVAL;
+    Ctx &c = h->c;
+    c.n = n;
+    c.nc = nc;
+    c.eps = eps;
+    c.cfg = *cfg;
+    c.cfg.cluster_offsets = nullptr;
+    c.stream = (hipStream_t)cfg->stream;
+    auto bail = [&](int rc) {
+        if (c.h_info)
+            (void)hipHostFree(c.h_info);
+        delete h;
+        return rc;
+    };
+    if (hipGetDevice(&c.device) != hipSuccess)
+        return bail(NBODY_EDEVICE);
+    ws_layout(n, nc, cfg->precision, &c, static_cast<char *>(d_workspace));
+    if (hipHostMalloc((void **)&c.h_info, 64 * sizeof(int64_t) + 64 * sizeof(double) + 64,
+                      hipHostMallocDefault) != hipSuccess)
+        return bail(NBODY_EDEVICE);
+    c.h_red = reinterpret_cast<double *>(c.h_info + 64);
+    c.h_err = reinterpret_cast<uint32_t *>(c.h_red + 64);
+    // cluster offsets, cluster of each particle, schedule chunk table
+    c.off.assign(nc + 1, 0);
+    if (nc > 1)
+        std::copy(cfg->cluster_offsets, cfg->cluster_offsets + nc + 1, c.off.begin());
+    else
+        c.off[1] = n;
+    std::vector<int32_t> ch_cl;
+    std::vector<int64_t> ch_b;
+    for (int32_t k = 0; k < nc; ++k)
+        for (int64_t b = c.off[k]; b < c.off[k + 1]; b += SCHED_CHUNK) {
+            ch_cl.push_back(k);
+            ch_b.push_back(b);
+        }
+    ch_b.push_back(n);
+    c.n_chunks = (int64_t)ch_cl.size();
+    hipStream_t s = c.stream;
+    int rc = NBODY_OK;
+    auto H = [&](hipError_t e, const char *w) {
+        if (e != hipSuccess && rc == NBODY_OK)
+            rc = hip_fail(c, e, w);
+    };
+    H(hipMemcpyAsync(c.d_off, c.off.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s), "offsets");
+    H(hipMemcpyAsync(c.d_chunk_cluster, ch_cl.data(), c.n_chunks * 4, hipMemcpyHostToDevice, s), "chunks");
+    H(hipMemcpyAsync(c.d_chunk_begin, ch_b.data(), (c.n_chunks + 1) * 8, hipMemcpyHostToDevice, s), "chunks");
+    if (nc > 1) {
+        std::vector<int32_t> cl(n);
+        for (int32_t k = 0; k < nc; ++k)
+            std::fill(cl.begin() + c.off[k], cl.begin() + c.off[k + 1], k);
+        H(hipMemcpyAsync(c.d_cluster_of, cl.data(), n * 4, hipMemcpyHostToDevice, s), "cluster_of");
+        H(hipStreamSynchronize(s), "sync");   // host vectors go out of scope
+    }
+    H(hipMemsetAsync(c.d_err, 0, 4, s), "err");
+    H(hipMemsetAsync(c.d_info, 0, 64 * 8, s), "info");
+    H(hipMemcpyAsync(c.st.mass, d_mass, n * 8, hipMemcpyDeviceToDevice, s), "mass");
+    H(launch_aos_to_soa(d_pos, c.st.pos, n, s), "pos");
+    H(launch_aos_to_soa(d_vel, c.st.vel, n, s), "vel");
+    H(hipMemsetAsync(c.st.acc, 0, 3 * n * 8, s), "acc");
+    H(hipMemsetAsync(c.st.jrk, 0, 3 * n * 8, s), "jrk");
+    H(hipMemsetAsync(c.st.snp, 0, 3 * n * 8, s), "snp");
+    H(hipMemsetAsync(c.st.crk, 0, 3 * n * 8, s), "crk");
+    H(hipMemsetAsync(c.st.t, 0, n * 8, s), "t");
+    H(launch_check_finite(c, s), "finite");
+    H(hipStreamSynchronize(s), "sync");
+    if (rc != NBODY_OK)
+        return bail(rc);
+    rc = take_err(c);
+    if (rc != NBODY_OK)
+        return bail(rc);
+    // initialization: pass 1 (a, da with zero source accelerations), pass 2
+    // (d2a with the pass-1 accelerations); then the first steps
+    for (int pass = 0; pass < 2 && rc == NBODY_OK; ++pass) {
+        H(launch_pack(c, nullptr, 1, nullptr, s), "pack");
+        H(launch_segments(c, nullptr, n, s), "segments");
+        ForceOut fo{};
+        fo.vec[0] = c.st.acc;
+        fo.vec[1] = c.st.jrk;
+        fo.vec[2] = c.st.snp;
+        fo.sk = 1;
+        fo.sd = n;
+        if (rc == NBODY_OK)
+            rc = run_force(c, nullptr, n, c.nc == 1 ? n : std::max<int64_t>(1, n / c.nc), fo);
+    }
+    H(launch_init_dt(c, s), "init_dt");
+    if (rc == NBODY_OK)
+        rc = take_err(c);
+    if (rc != NBODY_OK)
+        return bail(rc);
+    *out = h;
+    return NBODY_OK;
+}
+
+void nbody_free(nbody_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)prof_collect(ctx->c);
+    for (hipEvent_t e : ctx->c.prof_pool)
+        (void)hipEventDestroy(e);
+    if (ctx->c.h_info)
+        (void)hipHostFree(ctx->c.h_info);
+    delete ctx;
+}
+
+int nbody_force(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx, double *d_acc,
+                double *d_jrk, double *d_snp, double *d_pot)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (n_act < 0 || n_act > c.n)
+        return fail(c, NBODY_EINVAL, "n_act out of range");
+    if (n_act == 0)
+        return NBODY_OK;
+    if (!d_idx || !d_acc || !d_jrk || !d_snp)
+        return fail(c, NBODY_EINVAL, "null pointer");
+    if (c.cfg.validate) {
+        HIPCHK(c, launch_validate_idx(c, n_act, d_idx, c.stream));
+        const int rc = take_err(c);
+        if (rc)
+            return rc;
+    }
+    HIPCHK(c, launch_pack(c, nullptr, 1, nullptr, c.stream));
+    HIPCHK(c, launch_segments(c, d_idx, n_act, c.stream));
+    ForceOut out{};
+    out.vec[0] = d_acc;
+    out.vec[1] = d_jrk;
+    out.vec[2] = d_snp;
+    out.pot = d_pot;
+    out.sk = 3;
+    out.sd = 1;
+    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / c.nc);
+    return run_force(c, d_idx, n_act, typ, out, c.nc == 1 ? (double)n_act * (double)c.n : 0.0);
+}
+
+int nbody_predict(nbody_ctx *ctx, double t, double *d_pos, double *d_vel, double *d_acc)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (!d_pos || !d_vel || !d_acc || !std::isfinite(t))
+        return fail(c, NBODY_EINVAL, "bad argument");
+    HIPCHK(c, launch_predict_out(c, t, d_pos, d_vel, d_acc, c.stream));
+    return NBODY_OK;
+}
+
+int nbody_schedule(nbody_ctx *ctx, double t_target, int32_t *d_idx, int64_t *n_act,
+                   double *t_next)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (!d_idx || !n_act || !t_next || !on_grid(t_target, c.cfg.dt_min))
+        return fail(c, NBODY_EINVAL, "bad argument");
+    HIPCHK(c, launch_schedule(c, t_target, c.stream));
+    HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    *n_act = c.h_info[0];
+    std::memcpy(t_next, &c.h_info[1], 8);
+    if (*n_act > 0)
+        HIPCHK(c, hipMemcpyAsync(d_idx, c.act, *n_act * 4, hipMemcpyDeviceToDevice, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    return NBODY_OK;
+}
+
+int nbody_correct(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx, double t_target,
+                  const double *d_acc, const double *d_jrk, const double *d_snp)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (n_act < 0 || n_act > c.n || (n_act > 0 && (!d_idx || !d_acc || !d_jrk || !d_snp)) ||
+        !on_grid(t_target, c.cfg.dt_min))
+        return fail(c, NBODY_EINVAL, "bad argument");
+    HIPCHK(c, launch_correct(c, n_act, d_idx, t_target, d_acc, d_jrk, d_snp, 3, 1, c.stream));
+    return take_err(c);
+}
+
+int nbody_block_step(nbody_ctx *ctx, double t_target, int64_t *n_act, double *t_block)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (!n_act || !t_block || !on_grid(t_target, c.cfg.dt_min))
+        return fail(c, NBODY_EINVAL, "bad argument");
+    int rc = block_step(c, t_target, n_act, t_block, nullptr);
+    if (rc)
+        return rc;
+    return take_err(c);
+}
+
+int nbody_step(nbody_ctx *ctx, double t_target, nbody_step_stats *stats)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (!on_grid(t_target, c.cfg.dt_min))
+        return fail(c, NBODY_EINVAL, "t_target not a non-negative multiple of dt_min");
+    if (stats)
+        std::memset(stats, 0, sizeof *stats);
+    HIPCHK(c, hipMemsetAsync(c.d_info + 8, 0, 40 * 8, c.stream));
+    HIPCHK(c, launch_recap(c, t_target, c.stream));
+    int rc = take_err(c);
+    if (rc)
+        return rc;
+    for (;;) {
+        int64_t na = 0;
+        double tb = 0.0;
+        rc = block_step(c, t_target, &na, &tb, stats);
+        if (rc)
+            return rc;
+        if (na == 0)
+            break;
+    }
+    if (stats) {
+        HIPCHK(c, hipMemcpyAsync(c.h_info + 8, c.d_info + 8, 40 * 8, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        for (int b = 0; b < 40; ++b)
+            stats->hist[b] = c.h_info[8 + b];
+    }
+    return take_err(c);
+}
+
+int nbody_get_state(nbody_ctx *ctx, double *d_pos, double *d_vel, double *d_acc, double *d_jrk,
+                    double *d_snp, double *d_crk, double *d_t, double *d_dt)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    const double *src[6] = {c.st.pos, c.st.vel, c.st.acc, c.st.jrk, c.st.snp, c.st.crk};
+    double *dst[6] = {d_pos, d_vel, d_acc, d_jrk, d_snp, d_crk};
+    for (int q = 0; q < 6; ++q)
+        if (dst[q])
+            HIPCHK(c, launch_soa_to_aos(src[q], dst[q], c.n, c.stream));
+    if (d_t)
+        HIPCHK(c, hipMemcpyAsync(d_t, c.st.t, c.n * 8, hipMemcpyDeviceToDevice, c.stream));
+    if (d_dt)
+        HIPCHK(c, hipMemcpyAsync(d_dt, c.st.dt, c.n * 8, hipMemcpyDeviceToDevice, c.stream));
+    return NBODY_OK;
+}
+
+int nbody_set_state(nbody_ctx *ctx, const double *d_pos, const double *d_vel,
+                    const double *d_acc, const double *d_jrk, const double *d_snp,
+                    const double *d_crk, const double *d_t, const double *d_dt)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    const double *src[6] = {d_pos, d_vel, d_acc, d_jrk, d_snp, d_crk};
+    double *dst[6] = {c.st.pos, c.st.vel, c.st.acc, c.st.jrk, c.st.snp, c.st.crk};
+    for (int q = 0; q < 6; ++q)
+        if (src[q])
+            HIPCHK(c, launch_aos_to_soa(src[q], dst[q], c.n, c.stream));
+    if (d_t)
+        HIPCHK(c, hipMemcpyAsync(c.st.t, d_t, c.n * 8, hipMemcpyDeviceToDevice, c.stream));
+    if (d_dt)
+        HIPCHK(c, hipMemcpyAsync(c.st.dt, d_dt, c.n * 8, hipMemcpyDeviceToDevice, c.stream));
+    return NBODY_OK;
+}
+
+int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3])
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    HIPCHK(c, launch_segments(c, nullptr, c.n, c.stream));
+    ForceOut out{};
+    out.pot = c.d_phi;
+    out.sk = 1;
+    out.sd = c.n;
+    // potential-only FP64 pass (vec[0] == nullptr selects it)
+    const int64_t typ = c.nc == 1 ? c.n : std::max<int64_t>(1, c.n / c.nc);
+    Launch L0 = c.pinned;
+    c.pinned = Launch{};
+    int rc = run_force(c, nullptr, c.n, typ, out);
+    c.pinned = L0;
+    if (rc)
+        return rc;
+    const int rec = prof_begin(c, PH_ENERGY);
+    HIPCHK(c, launch_energy_sums(c, c.d_phi, c.d_red + c.red_cap - 8, c.stream));
+    prof_end(c, rec);
+    HIPCHK(c, hipMemcpyAsync(c.h_red, c.d_red + c.red_cap - 8, 5 * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    if (ekin)
+        *ekin = c.h_red[0];
+    if (epot)
+        *epot = c.h_red[1];
+    if (L) {
+        L[0] = c.h_red[2];
+        L[1] = c.h_red[3];
+        L[2] = c.h_red[4];
+    }
+    return NBODY_OK;
+}
+
+int nbody_set_launch(nbody_ctx *ctx, const nbody_launch *shape)
+{
+    if (!ctx || !shape)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (shape->lanes_per_i == 0 || shape->waves == 0 || shape->split == 0) {
+        c.pinned = Launch{};
+        return NBODY_OK;
+    }
+    const int l = shape->lanes_per_i;
+    if (l < 1 || l > 64 || (l & (l - 1)) || (shape->waves != 1 && shape->waves != 2 &&
+                                             shape->waves != 4) || shape->split < 1 ||
+        shape->split > 65535)
+        return fail(c, NBODY_EINVAL, "bad launch shape");
+    c.pinned.lpi = l;
+    c.pinned.waves = shape->waves;
+    c.pinned.split = shape->split;
+    return NBODY_OK;
+}
+
+int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape)
+{
+    if (!ctx || !shape || n_act < 1)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    Launch L = pick_launch(c, n_act, max_cluster(c));
+    while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
+        L.split >>= 1;
+    shape->lanes_per_i = L.lpi;
+    shape->waves = L.waves;
+    shape->split = L.split;
+    shape->reserved = 0;
+    return NBODY_OK;
+}
+
+int nbody_autotune(nbody_ctx *ctx, double max_ms)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (!(max_ms > 0.0))
+        max_ms = 200.0;
+    const int64_t nsrc = max_cluster(c);
+    hipStream_t s = c.stream;
+    // sources = the stored state; outputs to the integrator's scratch
+    HIPCHK(c, launch_pack(c, nullptr, 1, nullptr, s));
+    const bool was_prof = c.prof;
+    c.prof = false;
+    const Launch pinned = c.pinned;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    std::vector<Launch> table;
+    int rc = NBODY_OK;
+    std::vector<int32_t> hidx;
+    for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc; ++b) {
+        const int64_t na = int64_t(1) << b;
+        // evenly spread active particles of the first cluster
+        hidx.resize(na);
+        for (int64_t k = 0; k < na; ++k)
+            hidx[k] = (int32_t)(c.off[0] + k * nsrc / na);
+        if (hipMemcpyAsync(c.act, hidx.data(), na * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = hip_fail(c, hipGetLastError(), "autotune copy");
+            break;
+        }
+        if (c.nc > 1) {
+            if (launch_segments(c, c.act, na, s) != hipSuccess) {
+                rc = hip_fail(c, hipGetLastError(), "autotune segments");
+                break;
+            }
+        } else if (launch_segments(c, c.act, na, s) != hipSuccess) {
+            rc = hip_fail(c, hipGetLastError(), "autotune segments");
+            break;
+        }
+        ForceOut out{};
+        out.vec[0] = c.fnew;
+        out.vec[1] = c.fnew + 3 * na;
+        out.vec[2] = c.fnew + 6 * na;
+        out.sk = 1;
+        out.sd = na;
+        Launch best{};
+        float best_ms = 1e30f;
+        double spent = 0.0;
+        for (int waves : {4, 2, 1}) {
+            for (int lpi = 1; lpi <= 64; lpi <<= 1) {
+                for (int split = 1; split <= 4096; split <<= 1) {
+                    const int64_t lanes = na * lpi * split;
+                    if (lanes < (int64_t(1) << 14) && !(lpi == 64 && split >= nsrc / (64 * waves)))
+                        continue;   // too little parallelism (unless nothing more is possible)
+                    if (lanes > (int64_t(1) << 22) || split * na > c.part_cap)
+                        continue;
+                    if (split > 1 && nsrc / split < 64 * waves)
+                        continue;   // less than one tile per split
+                    if (64 * waves > 64 * 4 || na * lpi < 64 * waves / 4)
+                        continue;   // mostly idle workgroups
+                    c.pinned.lpi = lpi;
+                    c.pinned.waves = waves;
+                    c.pinned.split = split;
+                    float ms = 0.0f;
+                    bool ok = true;
+                    for (int rep = 0; rep < 3 && ok; ++rep) {
+                        ok = hipEventRecord(e0, s) == hipSuccess;
+                        ok = ok && run_force(c, c.act, na, na, out) == NBODY_OK;
+                        ok = ok && hipEventRecord(e1, s) == hipSuccess;
+                        ok = ok && hipEventSynchronize(e1) == hipSuccess;
+                        float t = 0.0f;
+                        ok = ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+                        if (rep > 0)
+                            ms = rep == 1 ? t : std::min(ms, t);
+                        spent += t;
+                    }
+                    if (!ok) {
+                        rc = hip_fail(c, hipGetLastError(), "autotune launch");
+                        break;
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = c.pinned;
+                    }
+                    if (spent > max_ms)
+                        break;
+                }
+                if (rc || spent > max_ms)
+                    break;
+            }
+            if (rc || spent > max_ms)
+                break;
+        }
+        table.push_back(best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.pinned = pinned;
+    c.prof = was_prof;
+    if (rc == NBODY_OK)
+        c.tuned = table;
+    return rc;
+}
+
+int nbody_profile(nbody_ctx *ctx, int enable, nbody_profile_times *out)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    HIPCHK(c, prof_collect(c));
+    if (out) {
+        for (int p = 0; p < NBODY_NPHASE; ++p) {
+            out->ms[p] = c.prof_ms[p];
+            out->launches[p] = c.prof_cnt[p];
+        }
+        out->pairs = c.prof_pairs;
+    }
+    if (enable && !c.prof) {
+        for (int p = 0; p < PH_N; ++p) {
+            c.prof_ms[p] = 0.0;
+            c.prof_cnt[p] = 0;
+        }
+        c.prof_pairs = 0.0;
+        c.flog_nact.clear();
+        c.flog_pairs.clear();
+        c.flog_ms.clear();
+    }
+    c.prof = enable != 0;
+    return NBODY_OK;
+}
+
+int64_t nbody_profile_force_log(nbody_ctx *ctx, int64_t max, int64_t *n_act, double *pairs,
+                                double *ms)
+{
+    if (!ctx)
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    if (prof_collect(c) != hipSuccess)
+        return NBODY_EDEVICE;
+    const int64_t n = (int64_t)c.flog_ms.size();
+    for (int64_t k = 0; k < std::min(n, max); ++k) {
+        if (n_act)
+            n_act[k] = c.flog_nact[k];
+        if (pairs)
+            pairs[k] = c.flog_pairs[k];
+        if (ms)
+            ms[k] = c.flog_ms[k];
+    }
+    return n;
+}
+
+}  // extern "C"

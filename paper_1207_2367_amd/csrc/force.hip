@@ -1,0 +1,410 @@
+// Evaluation step of the Hermite scheme on gfx950: acceleration, jerk, snap
+// and potential of the active particles against all sources of their
+// cluster (paper Sect. 3, item 2, with the softened potential of Sect. 2),
+// plus the split-source reduction (the paper's "Bfactor", Sect. 3).
+//
+// Design (CDNA4, wave64):
+//   - one workgroup = NW waves; each wave holds GI = 64 / LPI active
+//     particles, LPI lanes per particle; the i-particle lives in registers;
+//   - sources are staged through LDS in structure-of-arrays tiles of
+//     NT = 64 NW records, loaded coalesced by the whole workgroup; lane
+//     slot js of an i-particle takes tile entries js, js + LPI, ...; with
+//     LPI = 1 every LDS read is a broadcast;
+//   - the pair loop is pure vector ALU: no matrix cores, the work is not a
+//     dense contraction (every pair needs a reciprocal square root and
+//     nonlinear terms);
+//   - mixed precision: r_j - r_i in FP64, rounded to FP32, all other pair
+//     arithmetic in FP32 with v_rsq_f32; per-tile FP32 partial sums of a,
+//     da, d2a are folded into double-single (hi, lo) accumulators by an
+//     error-free two-sum, so the cross-tile sum carries ~48 bits; the
+//     potential terms (all of one sign) go straight into an FP64 sum;
+//   - the LPI lanes of a particle are combined by a xor butterfly of wave
+//     shuffles (bitwise identical on every lane, fixed order);
+//   - grid.y = B splits the sources; partial results go to a [B][10][n_act]
+//     buffer that a second kernel sums in fixed order b = 0 .. B-1, so the
+//     result does not depend on scheduling (no float atomics anywhere).
+#include "nbody_internal.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2;
+
+// Knuth's two-sum: (hi, lo) += p without rounding loss in the (hi, lo) pair.
+__device__ __forceinline__ void ds_add(float &hi, float &lo, float p)
+{
+    const float s = hi + p;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (p - bp);
+    hi = s;
+    lo += e;
+}
+
+// Far-away, massless stand-in for source slots past the end of a range.
+constexpr double NULL_POS = 1.0e15;
+
+template <int PREC>
+struct Smem;
+
+template <>
+struct Smem<PREC_MIXED> {
+    using R = JRecMixed;
+};
+template <>
+struct Smem<PREC_F64> {
+    using R = JRecF64;
+};
+template <>
+struct Smem<PREC_POT> {
+    using R = JRecF64;
+};
+
+template <int PREC, int LPI, int NW, bool EPS0>
+__global__ __launch_bounds__(NW * 64) void force_kernel(
+    typename Smem<PREC>::R J, ForceWork w, ForceOut out, double *part,
+    int64_t n_act_total, double eps2)
+{
+    constexpr int NT = NW * 64;      // sources per LDS tile
+    constexpr int GI = 64 / LPI;     // active particles per wave
+    constexpr int IB = NW * GI;      // active particles per workgroup
+    constexpr int PER = NT / LPI;    // pairs per lane per tile
+    constexpr bool MIXED = PREC == PREC_MIXED;
+    constexpr bool POT = PREC == PREC_POT;
+    using VT = typename std::conditional<MIXED, float, double>::type;
+
+    __shared__ double s_x[NT], s_y[NT], s_z[NT];
+    __shared__ VT s_m[NT];
+    __shared__ VT s_vx[POT ? 1 : NT], s_vy[POT ? 1 : NT], s_vz[POT ? 1 : NT];
+    __shared__ VT s_ax[POT ? 1 : NT], s_ay[POT ? 1 : NT], s_az[POT ? 1 : NT];
+
+    // ---- which active slots and which sources this workgroup takes
+    const int64_t g = blockIdx.x;
+    const int b = blockIdx.y;
+    int c = 0;
+    int64_t gfirst = 0;
+    if (w.blk_cluster) {
+        c = w.blk_cluster[g];
+        if (c < 0)
+            return;  // grid padding past the last i-block
+        gfirst = w.blk_first[c];
+    }
+    const int64_t s0 = w.seg[c], s1 = w.seg[c + 1];
+    const int64_t kb = s0 + (g - gfirst) * IB;
+    const int64_t o0 = w.off[c], o1 = w.off[c + 1];
+    int64_t chunk = (o1 - o0 + w.split - 1) / w.split;
+    chunk = (chunk + NT - 1) / NT * NT;
+    const int64_t j0 = o0 + (int64_t)b * chunk;
+    const int64_t j1 = j0 + chunk < o1 ? j0 + chunk : o1;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int il = wave * GI + lane / LPI;
+    const int js = lane & (LPI - 1);
+    const int64_t k = kb + il;
+    const bool valid = k < s1;
+    const int64_t kk = valid ? k : kb;
+    const int64_t i = w.idx ? (int64_t)w.idx[kk] : kk;
+
+    const double xi = J.x[i], yi = J.y[i], zi = J.z[i];
+    VT vxi = 0, vyi = 0, vzi = 0, axi = 0, ayi = 0, azi = 0;
+    if constexpr (!POT) {
+        vxi = J.vx[i]; vyi = J.vy[i]; vzi = J.vz[i];
+        axi = J.ax[i]; ayi = J.ay[i]; azi = J.az[i];
+    }
+    const VT e2 = (VT)eps2;
+
+    // accumulators: double-single pairs (mixed) or FP64 for a, da, d2a; the
+    // potential takes every FP32 pair term into an FP64 sum directly, so that
+    // the large j == i term (-m_i / eps) is removed exactly at the end
+    VT A[9], L[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        A[q] = 0;
+        L[q] = 0;
+    }
+    double phi = 0.0;
+
+    for (int64_t t0 = j0; t0 < j1; t0 += NT) {
+        __syncthreads();
+        const int64_t jj = t0 + tid;
+        if (jj < j1) {
+            s_x[tid] = J.x[jj];
+            s_y[tid] = J.y[jj];
+            s_z[tid] = J.z[jj];
+            s_m[tid] = J.m[jj];
+            if constexpr (!POT) {
+                s_vx[tid] = J.vx[jj]; s_vy[tid] = J.vy[jj]; s_vz[tid] = J.vz[jj];
+                s_ax[tid] = J.ax[jj]; s_ay[tid] = J.ay[jj]; s_az[tid] = J.az[jj];
+            }
+        } else {
+            s_x[tid] = NULL_POS;
+            s_y[tid] = NULL_POS;
+            s_z[tid] = NULL_POS;
+            s_m[tid] = 0;
+            if constexpr (!POT) {
+                s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
+                s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
+            }
+        }
+        __syncthreads();
+
+        VT T[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            T[q] = 0;
+
+#pragma unroll 4
+        for (int p = 0; p < PER; ++p) {
+            const int t = js + p * LPI;
+            const VT dx = (VT)(s_x[t] - xi);
+            const VT dy = (VT)(s_y[t] - yi);
+            const VT dz = (VT)(s_z[t] - zi);
+            const VT mj = s_m[t];
+            const VT r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
+            VT rinv;
+            if constexpr (MIXED)
+                rinv = __builtin_amdgcn_rsqf(r2);
+            else
+                rinv = rsqrt(r2);
+            if constexpr (EPS0)
+                rinv = r2 > (VT)0 ? rinv : (VT)0;
+            const VT mrinv = mj * rinv;
+            phi -= (double)mrinv;
+            if constexpr (!POT) {
+                const VT dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
+                const VT dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
+                const VT rinv2 = rinv * rinv;
+                const VT mr3 = mrinv * rinv2;
+                const VT rv = fma(dx, dvx, fma(dy, dvy, dz * dvz));
+                const VT qq = fma(dvx, dvx, fma(dvy, dvy, fma(dvz, dvz,
+                              fma(dx, dax, fma(dy, day, dz * daz)))));
+                const VT alpha = rv * rinv2;
+                const VT beta = fma(alpha, alpha, qq * rinv2);
+                const VT a3 = (VT)-3 * alpha;   // -3 alpha
+                const VT a6 = a3 + a3;          // -6 alpha
+                const VT b3 = (VT)-3 * beta;    // -3 beta
+                // J = mr3 (dv - 3 alpha dr); S = mr3 (da - 6 alpha jv - 3 beta dr)
+                const VT jx = fma(a3, dx, dvx), jy = fma(a3, dy, dvy), jz = fma(a3, dz, dvz);
+                const VT sx = fma(a6, jx, fma(b3, dx, dax));
+                const VT sy = fma(a6, jy, fma(b3, dy, day));
+                const VT sz = fma(a6, jz, fma(b3, dz, daz));
+                T[0] = fma(mr3, dx, T[0]);
+                T[1] = fma(mr3, dy, T[1]);
+                T[2] = fma(mr3, dz, T[2]);
+                T[3] = fma(mr3, jx, T[3]);
+                T[4] = fma(mr3, jy, T[4]);
+                T[5] = fma(mr3, jz, T[5]);
+                T[6] = fma(mr3, sx, T[6]);
+                T[7] = fma(mr3, sy, T[7]);
+                T[8] = fma(mr3, sz, T[8]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if constexpr (MIXED)
+                ds_add(A[q], L[q], T[q]);
+            else
+                A[q] += T[q];
+        }
+    }
+
+    // ---- combine the LPI lanes of each active particle (xor butterfly)
+    double R[10];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        R[q] = MIXED ? (double)A[q] + (double)L[q] : (double)A[q];
+    R[9] = phi;
+#pragma unroll
+    for (int msk = 1; msk < LPI; msk <<= 1) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            R[q] += __shfl_xor(R[q], msk, 64);
+    }
+
+    if (!valid || js != 0)
+        return;
+    // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
+    // potential: remove that term (computed the same way) when i was a source
+    if constexpr (!EPS0) {
+        if (i >= j0 && i < j1) {
+            const VT mi = J.m[i];
+            VT ri;
+            if constexpr (MIXED)
+                ri = __builtin_amdgcn_rsqf(fma((VT)0, (VT)0, fma((VT)0, (VT)0, fma((VT)0, (VT)0, e2))));
+            else
+                ri = rsqrt(e2);
+            R[9] += (double)(mi * ri);
+        }
+    }
+    if (part) {
+        double *pb = part + (int64_t)b * 10 * n_act_total + k;
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            pb[(int64_t)q * n_act_total] = R[q];
+    } else {
+        if constexpr (!POT) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
+        }
+        if (out.pot)
+            out.pot[k] = R[9];
+    }
+}
+
+// Sum the B split-source partials of every active slot in the fixed order
+// b = 0 .. B-1 (Table 1, section 4 of the paper).
+__global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t B,
+                                                    int64_t n_act, ForceOut out,
+                                                    int pot_only)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_act)
+        return;
+    double R[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        R[q] = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double *pb = part + (int64_t)b * 10 * n_act + k;
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            R[q] += pb[(int64_t)q * n_act];
+    }
+    if (!pot_only) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
+    }
+    if (out.pot)
+        out.pot[k] = R[9];
+}
+
+// ---- dispatch table over the template parameters
+using KMixed = void (*)(JRecMixed, ForceWork, ForceOut, double *, int64_t, double);
+using KF64 = void (*)(JRecF64, ForceWork, ForceOut, double *, int64_t, double);
+
+template <int PREC, bool EPS0, int NW>
+constexpr auto pick_lpi(int lpi_log2)
+{
+    using K = typename std::conditional<PREC == PREC_MIXED, KMixed, KF64>::type;
+    constexpr K tab[7] = {
+        force_kernel<PREC, 1, NW, EPS0>,  force_kernel<PREC, 2, NW, EPS0>,
+        force_kernel<PREC, 4, NW, EPS0>,  force_kernel<PREC, 8, NW, EPS0>,
+        force_kernel<PREC, 16, NW, EPS0>, force_kernel<PREC, 32, NW, EPS0>,
+        force_kernel<PREC, 64, NW, EPS0>};
+    return tab[lpi_log2];
+}
+
+template <int PREC, bool EPS0>
+auto pick_kernel(int lpi_log2, int nw)
+{
+    if (nw == 1)
+        return pick_lpi<PREC, EPS0, 1>(lpi_log2);
+    if (nw == 2)
+        return pick_lpi<PREC, EPS0, 2>(lpi_log2);
+    return pick_lpi<PREC, EPS0, 4>(lpi_log2);
+}
+
+int ilog2(int64_t v)
+{
+    int r = 0;
+    while ((int64_t(1) << (r + 1)) <= v)
+        ++r;
+    return r;
+}
+
+}  // namespace
+
+int64_t iblock_size(const Launch &L) { return (int64_t)L.waves * (64 / L.lpi); }
+
+// Heuristic launch shape (used until the autotuner has measured): enough
+// lanes to give every SIMD of the 256 CUs several waves, preferring the
+// split-source factor (coarse, cheap) and then lanes per particle.
+Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
+{
+    if (c.pinned.lpi > 0)
+        return c.pinned;
+    if (n_act >= 1 && !c.tuned.empty()) {
+        const int b = ilog2(n_act);
+        if (b < (int)c.tuned.size() && c.tuned[b].lpi > 0) {
+            Launch L = c.tuned[b];
+            while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
+                L.split >>= 1;
+            return L;
+        }
+    }
+    Launch L;
+    L.waves = 4;
+    L.lpi = 1;
+    L.split = 1;
+    const int64_t want_lanes = int64_t(256) * 4 * 64 * 8;  // 8 waves per SIMD
+    if (n_act < 256) {
+        L.waves = 1;
+    }
+    // lanes per particle first for tiny active sets, so that a wave is full
+    while (n_act * L.lpi < 64 * L.waves && L.lpi < 64)
+        L.lpi <<= 1;
+    const int64_t nt = 64 * L.waves;
+    auto lanes = [&](const Launch &q) { return n_act * q.lpi * q.split; };
+    // then split sources while every split keeps >= 4 tiles
+    while (lanes(L) < want_lanes && n_src / ((int64_t)L.split * 2) >= 4 * nt &&
+           (int64_t)L.split * 2 * n_act <= c.part_cap)
+        L.split <<= 1;
+    while (lanes(L) < want_lanes && L.lpi < 64)
+        L.lpi <<= 1;
+    return L;
+}
+
+hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
+                        const ForceOut &out, int64_t n_act_total, hipStream_t s)
+{
+    if (n_act_total <= 0 || w.n_blocks <= 0)
+        return hipSuccess;
+    const int lg = ilog2(L.lpi);
+    const bool eps0 = c.eps == 0.0;
+    const double eps2 = c.eps * c.eps;
+    double *part = w.split > 1 ? c.part : nullptr;
+    const dim3 grid((unsigned)w.n_blocks, (unsigned)w.split);
+    const dim3 block(64 * L.waves);
+    const int prec = out.vec[0] ? c.cfg.precision : PREC_POT;
+    const int rec = prof_begin(c, prec == PREC_POT ? PH_ENERGY : PH_FORCE, n_act_total);
+    if (prec == NBODY_PREC_MIXED) {
+        KMixed k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
+                        : pick_kernel<PREC_MIXED, false>(lg, L.waves);
+        hipLaunchKernelGGL(k, grid, block, 0, s, c.jm, w, out, part, n_act_total, eps2);
+    } else {
+        JRecF64 J = c.jd;
+        KF64 k;
+        if (prec == PREC_POT) {
+            // potential of the stored state: sources read straight from it
+            J.x = c.st.pos;
+            J.y = c.st.pos + c.n;
+            J.z = c.st.pos + 2 * c.n;
+            J.m = c.st.mass;
+            k = eps0 ? pick_kernel<PREC_POT, true>(lg, L.waves)
+                     : pick_kernel<PREC_POT, false>(lg, L.waves);
+        } else {
+            k = eps0 ? pick_kernel<PREC_F64, true>(lg, L.waves)
+                     : pick_kernel<PREC_F64, false>(lg, L.waves);
+        }
+        hipLaunchKernelGGL(k, grid, block, 0, s, J, w, out, part, n_act_total, eps2);
+    }
+    prof_end(c, rec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || w.split <= 1)
+        return e;
+    const unsigned nb = (unsigned)((n_act_total + 255) / 256);
+    const int rr = prof_begin(c, prec == PREC_POT ? PH_ENERGY : PH_REDUCE);
+    hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
+                       w.split, n_act_total, out, prec == PREC_POT ? 1 : 0);
+    prof_end(c, rr);
+    return hipGetLastError();
+}
+
+}  // namespace nb

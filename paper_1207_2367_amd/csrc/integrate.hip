@@ -1,0 +1,688 @@
+// Block-time-step machinery of the Hermite scheme on gfx950: prediction of
+// the sources (paper Sect. 3, item 1), active-set selection (Table 1,
+// section 1), corrector (item 3), interpolation of the higher derivatives,
+// the generalized Aarseth criterion (Eqs. indtstp, As) with power-of-two
+// block rules, and the energy / angular-momentum sums (Sect. 5.1).
+//
+// Everything here streams O(N) or O(N_act) FP64 data once, so the bound is
+// HBM bandwidth: kernels read structure-of-arrays state with one particle
+// per lane (coalesced), keep every per-particle temporary in registers and
+// write each output once.  Reductions run in a fixed tree order, so two
+// identical runs give identical bits.
+#include <cfloat>
+#include <cmath>
+
+#include "nbody_internal.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ double pow2_floor(double x)
+{
+    // largest power of two <= x for a positive normal x: keep the exponent
+    return __longlong_as_double(__double_as_longlong(x) & (long long)0xFFF0000000000000ULL);
+}
+
+__device__ __forceinline__ double norm3(double x, double y, double z)
+{
+    return sqrt(x * x + y * y + z * z);
+}
+
+// Block rules (reading of the paper's power-of-two quantization): round the
+// criterion down to a power of two, clamp to [dt_min, dt_max]; grow only by
+// doubling and only where t_new is a multiple of 2 dt_old; shrink freely;
+// while short of t_target, halve until t_new + dt <= t_target.
+// Returns 0, ERR_DTMIN or ERR_NONFINITE.
+__device__ uint32_t block_dt(double crit, double dt_old, double t_new, double t_target,
+                             double dt_min, double dt_max, double *dt_out)
+{
+    if (crit != crit)
+        return ERR_NONFINITE;
+    if (crit < dt_min)
+        return ERR_DTMIN;
+    double dt = dt_max;
+    if (crit < dt_max) {
+        dt = pow2_floor(crit);
+        if (dt < dt_min)
+            dt = dt_min;
+    }
+    if (dt_old > 0.0 && dt > dt_old) {
+        const double q = t_new / (2.0 * dt_old);   // exact: dyadic / power of two
+        dt = (q == floor(q)) ? 2.0 * dt_old : dt_old;
+    }
+    if (t_new < t_target) {
+        for (int it = 0; it < 80 && t_new + dt > t_target; ++it)
+            dt *= 0.5;
+    }
+    if (dt < dt_min)
+        return ERR_DTMIN;
+    *dt_out = dt;
+    return 0;
+}
+
+// ------------------------------------------------------------- predictor
+// Taylor series of paper Sect. 3 item 1 (Horner form) to the source
+// records.  T is the block time of the particle's cluster, or its own time
+// (h = 0: the records are the stored state) when own_time is set.
+__global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF64 jd,
+                                                   int prec, int64_t n, const double *Tc,
+                                                   const int32_t *cluster_of, int own_time)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double ti = st.t[i];
+    double h = 0.0;
+    if (!own_time) {
+        const double T = Tc[cluster_of ? cluster_of[i] : 0];
+        if (!(T < DBL_MAX))
+            return;  // cluster has reached the target: not a source this step
+        h = T - ti;
+    }
+    double xp[3], vp[3], ap[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = (int64_t)d * n + i;
+        const double x = st.pos[e], v = st.vel[e], a = st.acc[e];
+        const double j = st.jrk[e], s = st.snp[e], c = st.crk[e];
+        xp[d] = x + h * (v + h * (a * 0.5 + h * (j * (1.0 / 6) + h * (s * (1.0 / 24) + h * (c * (1.0 / 120))))));
+        vp[d] = v + h * (a + h * (j * 0.5 + h * (s * (1.0 / 6) + h * (c * (1.0 / 24)))));
+        ap[d] = a + h * (j + h * (s * 0.5 + h * (c * (1.0 / 6))));
+    }
+    const double m = st.mass[i];
+    if (prec == NBODY_PREC_MIXED) {
+        jm.x[i] = xp[0]; jm.y[i] = xp[1]; jm.z[i] = xp[2];
+        jm.vx[i] = (float)vp[0]; jm.vy[i] = (float)vp[1]; jm.vz[i] = (float)vp[2];
+        jm.ax[i] = (float)ap[0]; jm.ay[i] = (float)ap[1]; jm.az[i] = (float)ap[2];
+        jm.m[i] = (float)m;
+    } else {
+        jd.x[i] = xp[0]; jd.y[i] = xp[1]; jd.z[i] = xp[2];
+        jd.vx[i] = vp[0]; jd.vy[i] = vp[1]; jd.vz[i] = vp[2];
+        jd.ax[i] = ap[0]; jd.ay[i] = ap[1]; jd.az[i] = ap[2];
+        jd.m[i] = m;
+    }
+}
+
+// Predictor to FP64 [n][3] outputs at a common time t (diagnostic entry).
+__global__ __launch_bounds__(TPB) void predict_out_kernel(State st, int64_t n, double t,
+                                                          double *po, double *vo, double *ao)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double h = t - st.t[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = (int64_t)d * n + i;
+        const double x = st.pos[e], v = st.vel[e], a = st.acc[e];
+        const double j = st.jrk[e], s = st.snp[e], c = st.crk[e];
+        po[3 * i + d] = x + h * (v + h * (a * 0.5 + h * (j * (1.0 / 6) + h * (s * (1.0 / 24) + h * (c * (1.0 / 120))))));
+        vo[3 * i + d] = v + h * (a + h * (j * 0.5 + h * (s * (1.0 / 6) + h * (c * (1.0 / 24)))));
+        ao[3 * i + d] = a + h * (j + h * (s * 0.5 + h * (c * (1.0 / 6))));
+    }
+}
+
+// ---------------------------------------------------------- scheduling
+__global__ void sched_reset(uint64_t *tmin, int32_t nc)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc)
+        tmin[c] = ~0ull;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = __shfl_xor(v, m, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// per chunk: min over its particles of t + dt (as ordered bits; times are
+// >= 0 so the IEEE bits order like the values), into the cluster's slot
+__global__ __launch_bounds__(TPB) void sched_min(const double *t, const double *dt,
+                                                 const int64_t *chunk_begin,
+                                                 const int32_t *chunk_cluster, uint64_t *tmin)
+{
+    __shared__ uint64_t red[TPB / 64];
+    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
+    uint64_t v = ~0ull;
+    for (int64_t i = b + threadIdx.x; i < e; i += TPB) {
+        const uint64_t u = (uint64_t)__double_as_longlong(t[i] + dt[i]);
+        v = u < v ? u : v;
+    }
+    v = wave_min_u64(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = red[0];
+        for (int w = 1; w < TPB / 64; ++w)
+            m = red[w] < m ? red[w] : m;
+        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)m);
+    }
+}
+
+__device__ __forceinline__ bool due(double t, double dt, double T) { return t + dt == T; }
+
+__global__ __launch_bounds__(TPB) void sched_count(const double *t, const double *dt,
+                                                   const int64_t *chunk_begin,
+                                                   const int32_t *chunk_cluster,
+                                                   const uint64_t *tmin, double t_target,
+                                                   int32_t *cnt)
+{
+    __shared__ int red[TPB / 64];
+    const double T = __longlong_as_double((long long)tmin[chunk_cluster[blockIdx.x]]);
+    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
+    int c = 0;
+    if (T <= t_target)
+        for (int64_t i = b + threadIdx.x; i < e; i += TPB)
+            c += due(t[i], dt[i], T) ? 1 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < TPB / 64; ++w)
+            s += red[w];
+        cnt[blockIdx.x] = s;
+    }
+}
+
+// Single workgroup: exclusive scan of the chunk counts (chunks are in
+// particle order, so clusters are contiguous), per-cluster active
+// segments and block times, totals and the N_act histogram.
+// info[0] = N_act total, info[1] = bits of the earliest block time,
+// info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot.
+__global__ __launch_bounds__(1024) void sched_scan(const int32_t *cnt, int64_t n_chunks,
+                                                   const int32_t *chunk_cluster,
+                                                   const uint64_t *tmin, const int64_t *off,
+                                                   int32_t nc, double t_target,
+                                                   int64_t *chunk_pos, int64_t *seg,
+                                                   double *tblock, int64_t *info,
+                                                   int64_t *hist, const uint32_t *err)
+{
+    __shared__ int64_t buf[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0)
+        carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n_chunks; base += 1024) {
+        const int64_t q = base + threadIdx.x;
+        const int64_t v = q < n_chunks ? cnt[q] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 1024; s <<= 1) {
+            const int64_t add = threadIdx.x >= (unsigned)s ? buf[threadIdx.x - s] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (q < n_chunks)
+            chunk_pos[q] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023)
+            carry += buf[1023];
+        __syncthreads();
+    }
+    // segment starts: position of the first chunk of each cluster
+    for (int64_t q = threadIdx.x; q < n_chunks; q += 1024) {
+        const int32_t c = chunk_cluster[q];
+        if (q == 0 || chunk_cluster[q - 1] != c)
+            seg[c] = chunk_pos[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        seg[nc] = carry;
+        info[0] = carry;
+        double tmn = INFINITY;
+        int64_t pairs = 0;
+        for (int32_t c = 0; c < nc; ++c) {
+            const double T = __longlong_as_double((long long)tmin[c]);
+            const bool act = T <= t_target;
+            tblock[c] = act ? T : INFINITY;
+            if (act && T < tmn)
+                tmn = T;
+            const int64_t na = seg[c + 1] - seg[c];
+            pairs += na * (off[c + 1] - off[c]);
+            if (na > 0) {
+                int bb = 0;
+                while ((int64_t(1) << (bb + 1)) <= na)
+                    ++bb;
+                hist[bb] += 1;
+            }
+        }
+        info[1] = __double_as_longlong(tmn);
+        info[2] = pairs;
+        info[3] = (int64_t)*err;
+    }
+}
+
+// ordered compaction of the due particles of each chunk
+__global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const double *dt,
+                                                     const int64_t *chunk_begin,
+                                                     const int32_t *chunk_cluster,
+                                                     const double *tblock,
+                                                     const int64_t *chunk_pos, int32_t *act)
+{
+    __shared__ int wsum[TPB / 64];
+    const double T = tblock[chunk_cluster[blockIdx.x]];
+    if (!(T < DBL_MAX))
+        return;
+    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
+    int64_t pos = chunk_pos[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t base = b; base < e; base += TPB) {
+        const int64_t i = base + threadIdx.x;
+        const bool f = i < e && due(t[i], dt[i], T);
+        const uint64_t mask = __ballot(f);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < TPB / 64; ++w) {
+            woff += w < wave ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        if (f)
+            act[pos + woff + before] = (int32_t)i;
+        pos += tot;
+        __syncthreads();
+    }
+}
+
+// i-block tables of a force launch over clusters: cluster c gets
+// ceil(n_c / ib) blocks starting at blk_first[c]; the rest of the grid
+// (up to cap) is marked -1 (idle).
+__global__ __launch_bounds__(1024) void blocks_kernel(const int64_t *seg, int32_t nc, int64_t ib,
+                                                      int64_t cap, int64_t *blk_first,
+                                                      int32_t *blk_cluster)
+{
+    __shared__ int64_t total;
+    if (threadIdx.x == 0) {
+        int64_t g = 0;
+        for (int32_t c = 0; c < nc; ++c) {
+            blk_first[c] = g;
+            g += (seg[c + 1] - seg[c] + ib - 1) / ib;
+        }
+        blk_first[nc] = g;
+        total = g;
+    }
+    __syncthreads();
+    for (int32_t c = threadIdx.x; c < nc; c += 1024)
+        for (int64_t g = blk_first[c]; g < blk_first[c + 1]; ++g)
+            blk_cluster[g] = c;
+    for (int64_t g = total + threadIdx.x; g < cap; g += 1024)
+        blk_cluster[g] = -1;
+}
+
+// active segments of a caller's ascending index list: seg[c] = first slot
+// whose particle is >= off[c]
+__global__ void segments_kernel(const int32_t *idx, int64_t n_act, const int64_t *off,
+                                int32_t nc, int64_t *seg)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc)
+        return;
+    if (!idx) {  // identity list: every particle active
+        seg[c] = off[c];
+        return;
+    }
+    const int64_t key = off[c];
+    int64_t lo = 0, hi = n_act;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((int64_t)idx[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    seg[c] = c == nc ? n_act : lo;
+}
+
+__global__ void set_seg_kernel(int64_t *seg, int64_t a, int64_t b)
+{
+    seg[0] = a;
+    seg[1] = b;
+}
+
+// ----------------------------------------------------------- corrector
+// Corrector of paper Sect. 3 item 3 (velocity first, then position with the
+// corrected velocity), end-of-step crackle/pop/5th derivative from the
+// quintic through (a, da, d2a) at both ends, Aarseth criterion with p = 6,
+// block rules.  h is the particle's own step; its block time is t + dt.
+__global__ __launch_bounds__(TPB) void correct_kernel(
+    State st, int64_t n, int64_t n_act, const int32_t *idx, double t_target,
+    const double *fa, const double *fj, const double *fs, int64_t sk, int64_t sd,
+    double eta, double dt_min, double dt_max, uint32_t *err)
+{
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int64_t i = idx[k];
+    const double h = st.dt[i];
+    const double t_new = st.t[i] + h;
+    double a1[3], j1[3], s1[3], crk[3], pop[3], a5[3];
+    uint32_t bad = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = (int64_t)d * n + i;
+        a1[d] = fa[k * sk + d * sd];
+        j1[d] = fj[k * sk + d * sd];
+        s1[d] = fs[k * sk + d * sd];
+        const double a0 = st.acc[e], j0 = st.jrk[e], s0 = st.snp[e];
+        const double v0 = st.vel[e], r0 = st.pos[e];
+        const double v1 = v0 + h * 0.5 * (a1[d] + a0) - h * h * 0.1 * (j1[d] - j0) +
+                          h * h * h * (1.0 / 120) * (s1[d] + s0);
+        const double r1 = r0 + h * 0.5 * (v1 + v0) - h * h * 0.1 * (a1[d] - a0) +
+                          h * h * h * (1.0 / 120) * (j1[d] + j0);
+        // interpolation: C = c h^3, P = p h^4, X = x h^5 of the quintic
+        const double D0 = a1[d] - a0 - h * j0 - 0.5 * h * h * s0;
+        const double D1 = j1[d] - j0 - h * s0;
+        const double D2 = s1[d] - s0;
+        const double C = 60.0 * D0 - 24.0 * h * D1 + 3.0 * h * h * D2;
+        const double P = -360.0 * D0 + 168.0 * h * D1 - 24.0 * h * h * D2;
+        const double X = 720.0 * D0 - 360.0 * h * D1 + 60.0 * h * h * D2;
+        const double ih = 1.0 / h;
+        const double c0 = C * ih * ih * ih, p0 = P * ih * ih * ih * ih, x0 = X * ih * ih * ih * ih * ih;
+        crk[d] = c0 + h * p0 + 0.5 * h * h * x0;
+        pop[d] = p0 + h * x0;
+        a5[d] = x0;
+        if (!isfinite(r1) || !isfinite(v1))
+            bad |= ERR_NONFINITE;
+        st.pos[e] = r1;
+        st.vel[e] = v1;
+        st.acc[e] = a1[d];
+        st.jrk[e] = j1[d];
+        st.snp[e] = s1[d];
+        st.crk[e] = crk[d];
+    }
+    const double A1 = sqrt(norm3(a1[0], a1[1], a1[2]) * norm3(s1[0], s1[1], s1[2]) +
+                           j1[0] * j1[0] + j1[1] * j1[1] + j1[2] * j1[2]);
+    const double A4 = sqrt(norm3(crk[0], crk[1], crk[2]) * norm3(a5[0], a5[1], a5[2]) +
+                           pop[0] * pop[0] + pop[1] * pop[1] + pop[2] * pop[2]);
+    const double crit = A4 == 0.0 ? INFINITY : eta * cbrt(A1 / A4);
+    double dtn = h;
+    bad |= block_dt(crit, h, t_new, t_target, dt_min, dt_max, &dtn);
+    st.t[i] = t_new;
+    if (!bad)
+        st.dt[i] = dtn;
+    if (bad)
+        atomicOr(err, bad);
+}
+
+// first step after initialization: eta_init |a| / |da|
+__global__ __launch_bounds__(TPB) void init_dt_kernel(State st, int64_t n, double eta_init,
+                                                      double dt_min, double dt_max,
+                                                      uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double na = norm3(st.acc[i], st.acc[n + i], st.acc[2 * n + i]);
+    const double nj = norm3(st.jrk[i], st.jrk[n + i], st.jrk[2 * n + i]);
+    const double crit = nj > 0.0 ? eta_init * na / nj : INFINITY;
+    double dt = dt_max;
+    const uint32_t bad = block_dt(crit, 0.0, 0.0, INFINITY, dt_min, dt_max, &dt);
+    st.dt[i] = dt;
+    st.t[i] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        st.crk[(int64_t)d * n + i] = 0.0;
+    if (bad)
+        atomicOr(err, bad);
+}
+
+// start of a run: a particle short of t_target whose step passes it halves
+// the step until it does not; a particle past t_target is an error
+__global__ __launch_bounds__(TPB) void recap_kernel(State st, int64_t n, double t_target,
+                                                    uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double t = st.t[i];
+    double dt = st.dt[i];
+    if (t > t_target) {
+        atomicOr(err, ERR_BADIDX);
+        return;
+    }
+    if (t < t_target) {
+        for (int it = 0; it < 80 && t + dt > t_target; ++it)
+            dt *= 0.5;
+        st.dt[i] = dt;
+    }
+}
+
+// ------------------------------------------------------------- energy
+// per-workgroup partial sums of E_kin, (1/2) sum m phi, L; then one
+// workgroup adds the partials in order
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+        s += sh[w];
+    return s;
+}
+
+__global__ __launch_bounds__(TPB) void energy_partial(State st, int64_t n, const double *phi,
+                                                      double *red)
+{
+    __shared__ double sh[TPB / 64];
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    double q[5] = {0, 0, 0, 0, 0};
+    if (i < n) {
+        const double m = st.mass[i];
+        const double x = st.pos[i], y = st.pos[n + i], z = st.pos[2 * n + i];
+        const double vx = st.vel[i], vy = st.vel[n + i], vz = st.vel[2 * n + i];
+        q[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+        q[1] = 0.5 * m * phi[i];
+        q[2] = m * (y * vz - z * vy);
+        q[3] = m * (z * vx - x * vz);
+        q[4] = m * (x * vy - y * vx);
+    }
+    for (int r = 0; r < 5; ++r) {
+        const double s = block_sum(q[r], sh);
+        if (threadIdx.x == 0)
+            red[(int64_t)blockIdx.x * 5 + r] = s;
+    }
+}
+
+__global__ __launch_bounds__(1024) void energy_final(const double *red, int64_t nblk,
+                                                     double *out)
+{
+    __shared__ double sh[1024 / 64];
+    for (int r = 0; r < 5; ++r) {
+        double v = 0.0;
+        for (int64_t b = threadIdx.x; b < nblk; b += 1024)
+            v += red[b * 5 + r];
+        const double s = block_sum(v, sh);
+        if (threadIdx.x == 0)
+            out[r] = s;
+    }
+}
+
+// ------------------------------------------------------------ utilities
+__global__ void validate_idx_kernel(const int32_t *idx, int64_t n_act, int64_t n, uint32_t *err)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int32_t i = idx[k];
+    if (i < 0 || i >= n || (k > 0 && idx[k - 1] >= i))
+        atomicOr(err, ERR_BADIDX);
+}
+
+__global__ void aos_to_soa_kernel(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    dst[i] = src[3 * i];
+    dst[n + i] = src[3 * i + 1];
+    dst[2 * n + i] = src[3 * i + 2];
+}
+
+__global__ void soa_to_aos_kernel(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    dst[3 * i] = src[i];
+    dst[3 * i + 1] = src[n + i];
+    dst[3 * i + 2] = src[2 * n + i];
+}
+
+__global__ void check_finite_kernel(State st, int64_t n, uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    bool ok = isfinite(st.mass[i]);
+    for (int d = 0; d < 3; ++d)
+        ok = ok && isfinite(st.pos[(int64_t)d * n + i]) && isfinite(st.vel[(int64_t)d * n + i]);
+    if (!ok)
+        atomicOr(err, ERR_NONFINITE);
+}
+
+unsigned nblk(int64_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
+                       const int32_t *cluster_of, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.jm, c.jd,
+                       (int)c.cfg.precision, c.n, T_cluster, cluster_of, own_time);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel, double *acc,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(predict_out_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.n, t,
+                       pos, vel, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
+{
+    hipLaunchKernelGGL(sched_reset, dim3(nblk(c.nc)), dim3(TPB), 0, s, c.d_tmin, c.nc);
+    hipLaunchKernelGGL(sched_min, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
+                       (const double *)c.st.t, (const double *)c.st.dt,
+                       (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
+                       c.d_tmin);
+    hipLaunchKernelGGL(sched_count, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
+                       (const double *)c.st.t, (const double *)c.st.dt,
+                       (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
+                       (const uint64_t *)c.d_tmin, t_target, c.d_chunk_cnt);
+    hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const int32_t *)c.d_chunk_cnt,
+                       c.n_chunks, (const int32_t *)c.d_chunk_cluster,
+                       (const uint64_t *)c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
+                       c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info, c.d_info + 8,
+                       (const uint32_t *)c.d_err);
+    hipLaunchKernelGGL(sched_scatter, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
+                       (const double *)c.st.t, (const double *)c.st.dt,
+                       (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
+                       (const double *)c.d_tblock, (const int64_t *)c.d_chunk_pos, c.act);
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s)
+{
+    hipLaunchKernelGGL(blocks_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)c.d_seg,
+                       c.nc, ib, cap, c.d_blk_first, c.d_blk_cluster);
+    return hipGetLastError();
+}
+
+hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s)
+{
+    if (c.nc == 1 && idx) {
+        hipLaunchKernelGGL(set_seg_kernel, dim3(1), dim3(1), 0, s, c.d_seg, (int64_t)0, n_act);
+    } else {
+        hipLaunchKernelGGL(segments_kernel, dim3(nblk(c.nc + 1)), dim3(TPB), 0, s, idx, n_act,
+                           (const int64_t *)c.d_off, c.nc, c.d_seg);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx, double t_target,
+                          const double *fa, const double *fj, const double *fs, int64_t sk,
+                          int64_t sd, hipStream_t s)
+{
+    if (n_act <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(correct_kernel, dim3(nblk(n_act)), dim3(TPB), 0, s, c.st, c.n, n_act,
+                       idx, t_target, fa, fj, fs, sk, sd, c.cfg.eta, c.cfg.dt_min,
+                       c.cfg.dt_max, c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_recap(const Ctx &c, double t_target, hipStream_t s)
+{
+    hipLaunchKernelGGL(recap_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.n, t_target,
+                       c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_dt(const Ctx &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_dt_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.n,
+                       c.cfg.eta_init, c.cfg.dt_min, c.cfg.dt_max, c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_sums(const Ctx &c, const double *phi, double *out5, hipStream_t s)
+{
+    const unsigned nb = nblk(c.n);
+    hipLaunchKernelGGL(energy_partial, dim3(nb), dim3(TPB), 0, s, c.st, c.n, phi, c.d_red);
+    hipLaunchKernelGGL(energy_final, dim3(1), dim3(1024), 0, s, (const double *)c.d_red,
+                       (int64_t)nb, out5);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_idx(const Ctx &c, int64_t n_act, const int32_t *idx, hipStream_t s)
+{
+    if (n_act <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(validate_idx_kernel, dim3(nblk(n_act)), dim3(TPB), 0, s, idx, n_act,
+                       c.n, c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_aos_to_soa(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3(nblk(n)), dim3(TPB), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_soa_to_aos(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(soa_to_aos_kernel, dim3(nblk(n)), dim3(TPB), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const Ctx &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_finite_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.n,
+                       c.d_err);
+    return hipGetLastError();
+}
+
+}  // namespace nb

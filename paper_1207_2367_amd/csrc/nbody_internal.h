@@ -1,0 +1,174 @@
+// Internal declarations of the gfx950 N-body library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "nbody.h"
+
+namespace nb {
+
+// ---------------------------------------------------------------- records
+// Source ("j") records: the predicted state of every particle at the block
+// time, structure-of-arrays so that a tile load is coalesced.
+//   mixed: x, y, z in FP64 (for the FP64 differences r_j - r_i), velocity,
+//          acceleration and mass in FP32          -> 52 bytes per particle
+//   fp64 : every field FP64                       -> 80 bytes per particle
+struct JRecMixed {
+    double *x, *y, *z;
+    float *vx, *vy, *vz, *ax, *ay, *az, *m;
+};
+struct JRecF64 {
+    double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *m;
+};
+
+// Hermite state, FP64 structure-of-arrays: component d of particle i of
+// field f is f[d * n + i].  176 bytes per particle.
+struct State {
+    double *pos, *vel, *acc, *jrk, *snp, *crk;  // [3][n]
+    double *t, *dt, *mass;                      // [n]
+};
+
+// Where a force evaluation writes: component d of output q (0 acc, 1 jrk,
+// 2 snp) of active slot k goes to vec[q][k * sk + d * sd]; the potential to
+// pot[k] (pot may be null).
+struct ForceOut {
+    double *vec[3];
+    double *pot;
+    int64_t sk, sd;
+};
+
+// Work layout of one force launch over clusters.  Active slot k in
+// [seg[c], seg[c+1]) belongs to cluster c whose sources are
+// [off[c], off[c+1]).  i-block g of the launch covers slots
+// [seg[c] + (g - blk_first[c]) * IB, ...) of cluster c = blk_cluster[g]
+// (blk_cluster == nullptr: a single cluster, c = 0, blk_first = 0).
+struct ForceWork {
+    const int32_t *idx;       // active particle of each slot
+    const int64_t *seg;       // [nc + 1] device
+    const int64_t *off;       // [nc + 1] device
+    const int32_t *blk_cluster;
+    const int64_t *blk_first;
+    int64_t n_blocks;         // i-blocks in the grid (x dimension)
+    int32_t split;            // B, the split-source factor (grid y)
+    int32_t nc;
+};
+
+struct Launch {
+    int lpi = 0, waves = 0, split = 0;
+};
+
+struct Ctx;
+
+// force.hip
+hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
+                        const ForceOut &out, int64_t n_act_total, hipStream_t s);
+Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
+int64_t iblock_size(const Launch &L);
+
+// integrate.hip
+hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
+                       const int32_t *cluster_of, hipStream_t s);
+hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel,
+                              double *acc, hipStream_t s);
+hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
+hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
+hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
+                          double t_target, const double *fa, const double *fj,
+                          const double *fs, int64_t sk, int64_t sd, hipStream_t s);
+hipError_t launch_recap(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_energy_sums(const Ctx &c, const double *phi, double *out5,
+                              hipStream_t s);
+hipError_t launch_validate_idx(const Ctx &c, int64_t n_act, const int32_t *idx,
+                               hipStream_t s);
+hipError_t launch_aos_to_soa(const double *src, double *dst, int64_t n,
+                             hipStream_t s);
+hipError_t launch_soa_to_aos(const double *src, double *dst, int64_t n,
+                             hipStream_t s);
+hipError_t launch_check_finite(const Ctx &c, hipStream_t s);
+hipError_t launch_init_dt(const Ctx &c, hipStream_t s);
+
+// Device error word bits (set with atomicOr by kernels).
+enum : uint32_t { ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u };
+
+// Schedule scratch: chunk table built at init (a chunk never spans two
+// clusters), per-cluster block times and active segments.
+constexpr int SCHED_CHUNK = 2048;
+
+// Event-based timing of the phases of a block step (host side).
+enum Phase { PH_SCHED = 0, PH_PREDICT, PH_FORCE, PH_REDUCE, PH_CORRECT, PH_ENERGY, PH_N };
+struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+    int64_t n_act;
+    double pairs;
+};
+
+struct Ctx {
+    int64_t n = 0;
+    int32_t nc = 1;
+    double eps = 0.0;
+    nbody_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    State st{};
+    JRecMixed jm{};
+    JRecF64 jd{};
+    // [nc + 1] device copies of the cluster offsets, host copy too
+    int64_t *d_off = nullptr;
+    std::vector<int64_t> off;
+    int32_t *d_cluster_of = nullptr;  // [n] cluster of each particle (nc > 1)
+    // split-source partials: [B][10][n_act]
+    double *part = nullptr;
+    int64_t part_cap = 0;              // capacity in (B * n_act) units
+    // active list and new forces of the integrator: fnew[10][n]
+    int32_t *act = nullptr;
+    double *fnew = nullptr;
+    // scheduling
+    int64_t n_chunks = 0;
+    int32_t *d_chunk_cluster = nullptr;  // [n_chunks]
+    int64_t *d_chunk_begin = nullptr;    // [n_chunks + 1]
+    uint64_t *d_tmin = nullptr;          // [nc] bits of min(t+dt), per cluster
+    double *d_tblock = nullptr;          // [nc] block time, +inf if done
+    int32_t *d_chunk_cnt = nullptr;      // [n_chunks]
+    int64_t *d_chunk_pos = nullptr;      // [n_chunks]
+    int64_t *d_seg = nullptr;            // [nc + 1] active segments
+    int32_t *d_blk_cluster = nullptr;    // [n / 1 + nc] i-block -> cluster
+    int64_t *d_blk_first = nullptr;      // [nc + 1]
+    int64_t *d_info = nullptr;           // [64]: [0..7] step info, [8..47] N_act histogram
+    uint32_t *d_err = nullptr;           // device error word
+    double *d_red = nullptr;             // reduction scratch
+    int64_t red_cap = 0;
+    double *d_phi = nullptr;             // [n] potential scratch (energy)
+    // host pinned mirror for small readbacks
+    int64_t *h_info = nullptr;
+    double *h_red = nullptr;
+    uint32_t *h_err = nullptr;
+    // profiling
+    bool prof = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[PH_N] = {0};
+    int64_t prof_cnt[PH_N] = {0};
+    double prof_pairs = 0.0;
+    std::vector<int64_t> flog_nact;
+    std::vector<double> flog_pairs, flog_ms;
+    // launch choice
+    Launch pinned{};
+    std::vector<Launch> tuned;  // index: floor(log2(n_act))
+    std::string last_error;
+};
+
+int64_t ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base);
+
+// profiling marks (no-ops unless c.prof); prof_begin returns a record index
+int prof_begin(Ctx &c, int phase, int64_t n_act = 0, double pairs = 0.0);
+void prof_end(Ctx &c, int rec);
+hipError_t prof_collect(Ctx &c);
+
+}  // namespace nb

@@ -1,0 +1,286 @@
+"""ctypes binding of the C ABI in include/nbody.h.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory (inputs, outputs and the
+workspace) and the stream.  The library must have been built
+(``python -m paper_1207_2367_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libnbody.so")
+
+OK, EINVAL, EDEVICE, ENONFINITE, EDTMIN, ESTATE = 0, -1, -2, -3, -4, -5
+PREC_MIXED, PREC_FP64 = 0, 1
+
+_lib = None
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nbody error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("eta", C.c_double), ("eta_init", C.c_double), ("dt_min", C.c_double),
+        ("dt_max", C.c_double), ("precision", C.c_int32), ("n_clusters", C.c_int32),
+        ("cluster_offsets", C.POINTER(C.c_int64)), ("stream", C.c_void_p),
+        ("validate", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("block_steps", C.c_int64), ("active_total", C.c_int64),
+                ("interactions", C.c_double), ("hist", C.c_int64 * 40)]
+
+
+NPHASE = 6
+PHASES = ("schedule", "predict", "force", "reduce", "correct", "energy")
+
+
+class ProfileTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * NPHASE), ("launches", C.c_int64 * NPHASE),
+                ("pairs", C.c_double)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("lanes_per_i", C.c_int32), ("waves", C.c_int32), ("split", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+EXPORTS = [
+    "nbody_default_config", "nbody_workspace_bytes", "nbody_init", "nbody_free",
+    "nbody_force", "nbody_predict", "nbody_schedule", "nbody_correct", "nbody_block_step",
+    "nbody_step", "nbody_get_state", "nbody_set_state", "nbody_energy", "nbody_autotune",
+    "nbody_set_launch", "nbody_get_launch", "nbody_strerror", "nbody_last_error",
+    "nbody_profile", "nbody_profile_force_log",
+]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libnbody.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_1207_2367_amd.build`")
+    lib = C.CDLL(_LIB_PATH)
+    vp, i64, d, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int32
+    P = C.POINTER
+    sig = {
+        "nbody_default_config": (None, [P(Config)]),
+        "nbody_workspace_bytes": (C.c_size_t, [i64, P(Config)]),
+        "nbody_init": (C.c_int, [P(vp), i64, vp, vp, vp, d, P(Config), vp, C.c_size_t]),
+        "nbody_free": (None, [vp]),
+        "nbody_force": (C.c_int, [vp, i64, vp, vp, vp, vp, vp]),
+        "nbody_predict": (C.c_int, [vp, d, vp, vp, vp]),
+        "nbody_schedule": (C.c_int, [vp, d, vp, P(i64), P(d)]),
+        "nbody_correct": (C.c_int, [vp, i64, vp, d, vp, vp, vp]),
+        "nbody_block_step": (C.c_int, [vp, d, P(i64), P(d)]),
+        "nbody_step": (C.c_int, [vp, d, P(StepStats)]),
+        "nbody_get_state": (C.c_int, [vp] + [vp] * 8),
+        "nbody_set_state": (C.c_int, [vp] + [vp] * 8),
+        "nbody_energy": (C.c_int, [vp, P(d), P(d), P(d)]),
+        "nbody_autotune": (C.c_int, [vp, d]),
+        "nbody_set_launch": (C.c_int, [vp, P(Launch)]),
+        "nbody_get_launch": (C.c_int, [vp, i64, P(Launch)]),
+        "nbody_profile": (C.c_int, [vp, C.c_int, P(ProfileTimes)]),
+        "nbody_profile_force_log": (i64, [vp, i64, vp, vp, vp]),
+        "nbody_strerror": (C.c_char_p, [C.c_int]),
+        "nbody_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    load().nbody_default_config(C.byref(cfg))
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def workspace_bytes(n: int, cfg: Config) -> int:
+    return int(load().nbody_workspace_bytes(int(n), C.byref(cfg)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, shape, device):
+    t = torch.as_tensor(t, dtype=torch.float64, device=device).contiguous()
+    if tuple(t.shape) != tuple(shape):
+        t = t.reshape(shape).contiguous()
+    return t
+
+
+def _dev_i32(t, device):
+    return torch.as_tensor(t, device=device).to(torch.int32).contiguous()
+
+
+class System:
+    """One N-body system (or ensemble of clusters) resident on the GPU."""
+
+    def __init__(self, mass, pos, vel, eps, *, eta=0.45, eta_init=0.01,
+                 dt_min=2.0 ** -25, dt_max=1.0 / 16, precision=PREC_MIXED,
+                 offsets=None, validate=False, device="cuda"):
+        lib = load()
+        self.device = torch.device(device)
+        mass = _dev_f64(mass, (-1,), self.device)
+        n = self.n = mass.shape[0]
+        pos = _dev_f64(pos, (n, 3), self.device)
+        vel = _dev_f64(vel, (n, 3), self.device)
+        self._offsets = None
+        cfg = default_config(eta=eta, eta_init=eta_init, dt_min=dt_min, dt_max=dt_max,
+                             precision=precision, validate=1 if validate else 0)
+        if offsets is not None and len(offsets) > 2:
+            self._offsets = (C.c_int64 * len(offsets))(*[int(o) for o in offsets])
+            cfg.n_clusters = len(offsets) - 1
+            cfg.cluster_offsets = C.cast(self._offsets, C.POINTER(C.c_int64))
+        self.stream = torch.cuda.current_stream(self.device)
+        cfg.stream = C.c_void_p(self.stream.cuda_stream)
+        self.cfg = cfg
+        self.eps = float(eps)
+        ws = workspace_bytes(n, cfg)
+        if ws == 0:
+            raise NBodyError(EINVAL, "invalid configuration")
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        ctx = C.c_void_p()
+        rc = lib.nbody_init(C.byref(ctx), n, _ptr(mass), _ptr(pos), _ptr(vel), self.eps,
+                            C.byref(cfg), _ptr(self.workspace), ws)
+        if rc != OK:
+            raise NBodyError(rc, lib.nbody_strerror(rc).decode())
+        self.ctx = ctx
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, rc):
+        if rc != OK:
+            msg = load().nbody_last_error(self.ctx).decode()
+            raise NBodyError(rc, msg or load().nbody_strerror(rc).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().nbody_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- the ABI
+    def force(self, idx, out=None, pot=True):
+        """a, da, d2a, potential of particles ``idx`` (ascending) from the
+        stored state of all sources of their cluster."""
+        idx = _dev_i32(idx, self.device)
+        na = idx.shape[0]
+        if out is None:
+            out = [torch.empty((na, 3), dtype=torch.float64, device=self.device) for _ in range(3)]
+            out.append(torch.empty(na, dtype=torch.float64, device=self.device) if pot else None)
+        rc = load().nbody_force(self.ctx, na, _ptr(idx), *[_ptr(o) for o in out])
+        self._check(rc)
+        return tuple(out)
+
+    def predict(self, t):
+        outs = [torch.empty((self.n, 3), dtype=torch.float64, device=self.device) for _ in range(3)]
+        self._check(load().nbody_predict(self.ctx, float(t), *[_ptr(o) for o in outs]))
+        return tuple(outs)
+
+    def schedule(self, t_target):
+        idx = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        na, tn = C.c_int64(0), C.c_double(0.0)
+        self._check(load().nbody_schedule(self.ctx, float(t_target), _ptr(idx), C.byref(na),
+                                          C.byref(tn)))
+        return idx[: na.value], tn.value
+
+    def correct(self, idx, t_target, acc, jrk, snp):
+        idx = _dev_i32(idx, self.device)
+        na = idx.shape[0]
+        ins = [_dev_f64(q, (na, 3), self.device) for q in (acc, jrk, snp)]
+        self._check(load().nbody_correct(self.ctx, na, _ptr(idx), float(t_target),
+                                         *[_ptr(q) for q in ins]))
+
+    def block_step(self, t_target):
+        na, tb = C.c_int64(0), C.c_double(0.0)
+        self._check(load().nbody_block_step(self.ctx, float(t_target), C.byref(na), C.byref(tb)))
+        return na.value, tb.value
+
+    def step(self, t_target):
+        st = StepStats()
+        self._check(load().nbody_step(self.ctx, float(t_target), C.byref(st)))
+        return {"block_steps": st.block_steps, "active_total": st.active_total,
+                "interactions": st.interactions, "hist": list(st.hist)}
+
+    def get_state(self):
+        n = self.n
+        vec = [torch.empty((n, 3), dtype=torch.float64, device=self.device) for _ in range(6)]
+        sc = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
+        self._check(load().nbody_get_state(self.ctx, *[_ptr(q) for q in vec + sc]))
+        keys = ("x", "v", "a", "jk", "sn", "cr", "t", "dt")
+        return dict(zip(keys, vec + sc))
+
+    def set_state(self, x=None, v=None, a=None, jk=None, sn=None, cr=None, t=None, dt=None):
+        n = self.n
+        vec = [None if q is None else _dev_f64(q, (n, 3), self.device) for q in (x, v, a, jk, sn, cr)]
+        sc = [None if q is None else _dev_f64(q, (n,), self.device) for q in (t, dt)]
+        self._check(load().nbody_set_state(self.ctx, *[_ptr(q) for q in vec + sc]))
+        torch.cuda.synchronize(self.device)
+
+    def energy(self):
+        ek, ep, L = C.c_double(0), C.c_double(0), (C.c_double * 3)()
+        self._check(load().nbody_energy(self.ctx, C.byref(ek), C.byref(ep), L))
+        return ek.value, ep.value, [L[0], L[1], L[2]]
+
+    def autotune(self, max_ms=200.0):
+        self._check(load().nbody_autotune(self.ctx, float(max_ms)))
+
+    def set_launch(self, lanes_per_i=0, waves=0, split=0):
+        sh = Launch(int(lanes_per_i), int(waves), int(split), 0)
+        self._check(load().nbody_set_launch(self.ctx, C.byref(sh)))
+
+    def profile(self, enable):
+        """Start (enable=True, clears) or stop event timing of the phases;
+        returns the totals so far as {phase: (ms, launches)} plus pairs."""
+        pt = ProfileTimes()
+        self._check(load().nbody_profile(self.ctx, 1 if enable else 0, C.byref(pt)))
+        out = {ph: (pt.ms[k], pt.launches[k]) for k, ph in enumerate(PHASES)}
+        out["pairs"] = pt.pairs
+        return out
+
+    def force_log(self):
+        """Per-launch force-kernel records: (n_act, pairs, ms) arrays."""
+        import numpy as np
+        lib = load()
+        n = lib.nbody_profile_force_log(self.ctx, 0, None, None, None)
+        if n < 0:
+            self._check(int(n))
+        na = np.zeros(n, dtype=np.int64)
+        pr = np.zeros(n)
+        ms = np.zeros(n)
+        lib.nbody_profile_force_log(self.ctx, n, na.ctypes.data_as(C.c_void_p),
+                                    pr.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p))
+        return na, pr, ms
+
+    def get_launch(self, n_act):
+        sh = Launch()
+        self._check(load().nbody_get_launch(self.ctx, int(n_act), C.byref(sh)))
+        return sh.lanes_per_i, sh.waves, sh.split

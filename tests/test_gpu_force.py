@@ -1,0 +1,182 @@
+"""GPU parity of the evaluation step (paper Sect. 3, item 2, softened as in
+Sect. 2) through the C ABI: the mixed-precision and the FP64 kernels against
+the FP64 oracle, element by element, on seeded Plummer inputs.
+
+Tolerance (per particle i and quantity Q, relative error
+err_i(Q) = ||Q_gpu - Q_oracle|| / ||Q_oracle||):
+
+    err_i(Q) <= TOL * kappa_i(Q),   kappa_i(Q) = sum_j |Q_ij| / |sum_j Q_ij| >= 1
+
+mixed: TOL = 1e-6 (a, da, potential), 2e-6 (d2a).  Derivation: a pair term
+  evaluated in FP32 (unit roundoff u = 2^-24 = 6e-8) carries about a dozen
+  roundings (difference, r^2, rsqrt, r^-3, alpha, beta, the products), i.e.
+  a relative error of at most ~16 u = 1e-6; a sum of such terms is off by at
+  most that times its condition number kappa_i.  For well-conditioned sums
+  (kappa ~ 1, always for the potential) this is the 1e-6 per-particle
+  target; particles whose jerk or snap nearly cancels (kappa up to ~30 in a
+  Plummer sphere) get the proportionally larger bound, which no FP32
+  evaluation of the pair terms can beat.  The snap pair term has one more
+  cancelling level (-6 alpha J - 3 beta A), hence 2e-6.
+fp64: TOL = 1e-12 / 1e-11 by the same argument at u = 1.1e-16.
+The tests print the plain max / p99 / median errors and the fraction of
+particles within 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import ics
+import oracle
+from gpu_helpers import cpu, gpu_system, kappa, log_case, plummer_inputs, rel_err_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: (1e-6, 2e-6), 1: (1e-12, 1e-11)}   # precision -> (a/da/pot, d2a)
+EPS = 1e-4
+
+
+def _check(prec, got, ref, kap):
+    ta, ts = TOL[prec]
+    ga, gj, gs, gp = (cpu(q) for q in got)
+    ra, rj, rs, rp = ref
+    errs = [rel_err_rows(ga, ra), rel_err_rows(gj, rj), rel_err_rows(gs, rs),
+            rel_err_rows(gp, rp)]
+    worst = [float(e.max()) for e in errs]
+    print("max rel err a %.2e da %.2e d2a %.2e pot %.2e" % tuple(worst), flush=True)
+    print("p99 %s | within 1e-6: %s | max kappa %s" % (
+        [f"{np.percentile(e, 99):.1e}" for e in errs],
+        [f"{(e <= 1e-6).mean():.4f}" for e in errs],
+        [f"{k:.1f}" for k in kap.max(0)]), flush=True)
+    for q, e in enumerate(errs):
+        bound = (ts if q == 2 else ta) * kap[:, q]
+        bad = np.nonzero(e > bound)[0]
+        assert bad.size == 0, (q, bad[:5], e[bad[:5]], kap[bad[:5], q])
+    return worst
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    n = 5000 + 77     # several tiles of every size and a ragged tail
+    return plummer_inputs(n, 2002)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("n_act", [1, 7, 64, 333, 5077])
+def test_force_parity(inputs, prec, n_act):
+    m, x, v, a = inputs
+    n = m.shape[0]
+    log_case(test="force_parity", prec=prec, n=n, n_act=n_act)
+    idx = ics.active_subset(n, n_act, 7 + n_act)
+    ref = oracle.force(m, x, v, a, EPS, idx)
+    s = gpu_system(m, x, v, a, EPS, prec)
+    got = s.force(idx)
+    torch.cuda.synchronize()
+    _check(prec, got, ref, kappa(m, x, v, a, EPS, idx))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_every_launch_shape(inputs, prec):
+    """Each lanes-per-particle / waves / split-source shape gives the same
+    result to the tolerance (fixed-order reductions)."""
+    m, x, v, a = inputs
+    n = m.shape[0]
+    idx = ics.active_subset(n, 150, 5)
+    ref = oracle.force(m, x, v, a, EPS, idx)
+    kap = kappa(m, x, v, a, EPS, idx)
+    s = gpu_system(m, x, v, a, EPS, prec)
+    for lpi in (1, 2, 4, 8, 16, 32, 64):
+        for waves in (1, 2, 4):
+            for split in (1, 3, 16):
+                log_case(test="launch_shape", prec=prec, lpi=lpi, waves=waves, split=split)
+                s.set_launch(lpi, waves, split)
+                got = s.force(idx)
+                torch.cuda.synchronize()
+                _check(prec, got, ref, kap)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_deterministic(inputs, prec):
+    m, x, v, a = inputs
+    idx = ics.active_subset(m.shape[0], 1000, 3)
+    s = gpu_system(m, x, v, a, EPS, prec)
+    r1 = [cpu(q).copy() for q in s.force(idx)]
+    r2 = [cpu(q).copy() for q in s.force(idx)]
+    for p, q in zip(r1, r2):
+        assert np.array_equal(p, q)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_unsoftened_kepler(prec):
+    """eps = 0 (masked self pair): circular binary closed forms plus a few
+    far particles of negligible mass."""
+    m1, m2, R = 0.25, 0.75, 0.8
+    M = m1 + m2
+    w = np.sqrt(M / R ** 3)
+    u = np.array([np.cos(0.7), np.sin(0.7), 0.0])
+    ut = np.array([-np.sin(0.7), np.cos(0.7), 0.0])
+    x = np.array([-(m2 / M) * R * u, (m1 / M) * R * u])
+    v = np.array([-(m2 / M) * R * w * ut, (m1 / M) * R * w * ut])
+    a = -w * w * x
+    log_case(test="kepler_eps0", prec=prec)
+    s = gpu_system(np.array([m1, m2]), x, v, a, 0.0, prec)
+    ga, gj, gs, gp = (cpu(q) for q in s.force([0, 1]))
+    tol = 1e-6 if prec == 0 else 1e-13
+    assert np.abs(ga + w ** 2 * x).max() < tol * w ** 2 * R
+    assert np.abs(gj + w ** 2 * v).max() < tol * w ** 3 * R
+    assert np.abs(gs - w ** 4 * x).max() < 4 * tol * w ** 4 * R
+    np.testing.assert_allclose(gp, [-m2 / R, -m1 / R], rtol=tol)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_clusters(prec):
+    """Independent clusters: each particle only feels its own cluster."""
+    sizes = [300, 77, 1200, 256, 640]
+    m, x, v, off = ics.king_ensemble(len(sizes), sizes=sizes)
+    a = ics.random_vectors(m.size, 4, 0.5)
+    idx = np.sort(np.concatenate([ics.active_subset(sizes[c], max(1, sizes[c] // 5), c) + off[c]
+                                  for c in range(len(sizes))]))
+    log_case(test="clusters", prec=prec, n=m.size, n_act=idx.size)
+    ref = [np.zeros((idx.size, 3)) for _ in range(3)] + [np.zeros(idx.size)]
+    kap = np.zeros((idx.size, 4))
+    for c in range(len(sizes)):
+        sel = (idx >= off[c]) & (idx < off[c + 1])
+        r = oracle.force(m, x, v, a, EPS, idx[sel], (off[c], off[c + 1]))
+        kap[sel] = kappa(m, x, v, a, EPS, idx[sel], (off[c], off[c + 1]))
+        for q in range(4):
+            ref[q][sel] = r[q]
+    s = gpu_system(m, x, v, a, EPS, prec, offsets=off)
+    for shape in ((0, 0, 0), (1, 4, 1), (8, 1, 4), (64, 1, 2)):
+        s.set_launch(*shape)
+        _check(prec, s.force(idx), ref, kap)
+
+
+def test_force_validate_rejects_bad_index():
+    from paper_1207_2367_amd import NBodyError
+    m, x, v, a = plummer_inputs(512, 1)
+    s = gpu_system(m, x, v, a, EPS, 0, validate=True)
+    s.force([1, 5, 9])
+    for bad in ([3, 2], [0, 512], [-1, 4], [4, 4]):
+        with pytest.raises(NBodyError) as e:
+            s.force(bad)
+        assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_full_size_sampled(prec):
+    """The N = 65,536 Plummer sphere with every particle active, in the
+    launch shape the benchmark uses: 256 sampled particles against the
+    oracle, one by one."""
+    n = 65536
+    m, x, v, a = plummer_inputs(n, 2002)
+    log_case(test="full_size", prec=prec, n=n)
+    s = gpu_system(m, x, v, a, EPS, prec)
+    idx = np.arange(n)
+    got = [cpu(q) for q in s.force(idx)]
+    sample = ics.active_subset(n, 256, 99)
+    ref = oracle.force(m, x, v, a, EPS, sample)
+    _check(prec, [torch.as_tensor(g[sample]) for g in got], ref,
+           kappa(m, x, v, a, EPS, sample))
+    # third law over the whole system
+    mm = m[:, None]
+    scale = np.abs(mm * got[0]).sum()
+    assert np.abs((mm * got[0]).sum(0)).max() < (1e-6 if prec == 0 else 1e-13) * scale
