@@ -46,7 +46,7 @@ extern "C" {
 
 typedef struct nbody_config {
     double eta;      /* accuracy parameter of the step criterion, > 0     */
-    double eta_init; /* first step = power of two below eta_init |a|/|da| */
+    double eta_init; /* first step: eta_init A(1)/A(2) (p = 4), see init   */
     double dt_min;   /* smallest block step, a power of two               */
     double dt_max;   /* largest block step, a power of two >= dt_min      */
     int32_t precision;  /* NBODY_PREC_MIXED or NBODY_PREC_FP64            */
@@ -71,7 +71,7 @@ typedef struct nbody_step_stats {
     int64_t hist[40];
 } nbody_step_stats;
 
-/* Fill *cfg with the defaults: eta 0.45, eta_init 0.01, dt_min 2^-25,
+/* Fill *cfg with the defaults: eta 0.45, eta_init 0.1, dt_min 2^-25,
    dt_max 1/16, mixed precision, one system, default stream.            */
 void nbody_default_config(nbody_config *cfg);
 
@@ -85,10 +85,14 @@ size_t nbody_workspace_bytes(int64_t n, const nbody_config *cfg);
    and softening eps >= 0 (the softened potential of paper Sect. 2,
    Eq. softpot).  d_workspace must hold nbody_workspace_bytes(n, cfg)
    bytes, 256-byte aligned, and stay alive until nbody_free.
-   Initialization (the paper does not describe it): acceleration and jerk
-   of every particle, then a second evaluation with those accelerations for
-   the snap; crackle = 0; t_i = 0; first step = the power of two below
-   eta_init |a| / |da|, clamped to [dt_min, dt_max].  Synchronizes.
+   Initialization (the paper does not describe it), in FP64 whatever the
+   precision: acceleration and jerk of every particle, then a second
+   evaluation with those as the sources' values for the snap and the
+   crackle (the third derivative, by the same pairwise differentiation);
+   t_i = 0; first step = the paper's generalized criterion (Eqs. indtstp,
+   As) at the order these derivatives allow, p = 4: eta_init A(1)/A(2),
+   A(2) = sqrt(|da||a(3)| + |d2a|^2), rounded down to a power of two and
+   clamped to [dt_min, dt_max].  Synchronizes.
    Errors: EINVAL (n <= 0, eps < 0 or not finite, eta or eta_init <= 0,
    dt bounds not powers of two or dt_min > dt_max, bad cluster offsets,
    NULL pointer, workspace too small or misaligned), EDEVICE,

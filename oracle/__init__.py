@@ -53,6 +53,8 @@ def _load():
     d, i64, vp = C.c_double, C.c_int64, C.c_void_p
     lib.orc_force.argtypes = [i64, vp, vp, vp, vp, d, i64, i64, i64, vp, vp, vp, vp, vp]
     lib.orc_force.restype = None
+    lib.orc_force4.argtypes = [i64, vp, vp, vp, vp, vp, d, i64, i64, i64, vp, vp, vp, vp, vp]
+    lib.orc_force4.restype = None
     lib.orc_predict.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, d, vp, vp, vp]
     lib.orc_predict.restype = None
     lib.orc_interpolate.argtypes = [d, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -116,6 +118,23 @@ def force(mass, pos, vel, acc, eps, idx=None, j_range=None):
     out = [np.zeros((na, 3)) for _ in range(3)] + [np.zeros(na)]
     lib.orc_force(n, _p(m), _p(x), _p(v), _p(a), float(eps), int(j0), int(j1), na,
                   _p(idx), *[_p(o) for o in out])
+    return tuple(out)
+
+
+def force4(mass, pos, vel, acc, jrk, eps, idx=None, j_range=None):
+    """a, da, d2a and the crackle of the particles ``idx`` (the evaluation
+    of paper Sect. 3 item 2 extended by one derivative, used at the start).
+    Returns (acc, jrk, snp, crk), each [n_act, 3]."""
+    lib = _load()
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v, a, j = (_f64(q, (n, 3)) for q in (pos, vel, acc, jrk))
+    idx = _i64(np.arange(n) if idx is None else idx)
+    j0, j1 = (0, n) if j_range is None else j_range
+    na = idx.shape[0]
+    out = [np.zeros((na, 3)) for _ in range(4)]
+    lib.orc_force4(n, _p(m), _p(x), _p(v), _p(a), _p(j), float(eps), int(j0), int(j1), na,
+                   _p(idx), *[_p(o) for o in out])
     return tuple(out)
 
 
@@ -187,7 +206,7 @@ class Integrator:
     """Whole block-step Hermite-6 integration of one system or of several
     independent clusters (``offsets``), paper Sect. 3 and Table 1."""
 
-    def __init__(self, mass, pos, vel, eps, eta=0.45, eta_init=0.01,
+    def __init__(self, mass, pos, vel, eps, eta=0.45, eta_init=0.1,
                  dt_min=2.0 ** -25, dt_max=1.0 / 16, offsets=None):
         self.m = _f64(mass).copy()
         n = self.n = self.m.shape[0]

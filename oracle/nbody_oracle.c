@@ -100,6 +100,71 @@ void orc_force(int64_t n, const double *m, const double *x, const double *v,
 }
 
 /* ------------------------------------------------------------------ */
+/* O1'. The same sums and, in addition, the crackle (third derivative  */
+/* of the acceleration), needed once at the start (O7).  It is the    */
+/* time derivative of the snap term along the trajectories, with the  */
+/* sources' jerks j_j entering through q = j_j - j_i:                 */
+/*   gamma r^2 = 3 v.a + r.q + alpha (3 beta - 4 alpha^2) r^2         */
+/*   C = m_j q / r^3 - 9 alpha S - 9 beta J - 3 gamma A               */
+/* (softened distance throughout, as in O1).                          */
+/* ------------------------------------------------------------------ */
+void orc_force4(int64_t n, const double *m, const double *x, const double *v,
+                const double *a, const double *jk, double eps, int64_t j0,
+                int64_t j1, int64_t n_act, const int64_t *idx, double *acc,
+                double *jrk, double *snp, double *crk)
+{
+    const double eps2 = eps * eps;
+    (void)n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_act; ++k) {
+        const int64_t i = idx[k];
+        double ai[3] = {0, 0, 0}, ji[3] = {0, 0, 0}, si[3] = {0, 0, 0};
+        double ci[3] = {0, 0, 0};
+        for (int64_t j = j0; j < j1; ++j) {
+            if (j == i)
+                continue;
+            double r[3], w[3], q[3], u[3];
+            for (int d = 0; d < 3; ++d) {
+                r[d] = x[3 * j + d] - x[3 * i + d];
+                w[d] = v[3 * j + d] - v[3 * i + d];
+                q[d] = a[3 * j + d] - a[3 * i + d];
+                u[d] = jk[3 * j + d] - jk[3 * i + d];
+            }
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+            const double rinv = 1.0 / sqrt(r2);
+            const double rinv2 = rinv * rinv;
+            const double mr3 = m[j] * rinv * rinv2;
+            const double rv = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+            const double vv = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+            const double ra = r[0] * q[0] + r[1] * q[1] + r[2] * q[2];
+            const double va = w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+            const double rj = r[0] * u[0] + r[1] * u[1] + r[2] * u[2];
+            const double alpha = rv * rinv2;
+            const double beta = (vv + ra) * rinv2 + alpha * alpha;
+            const double gamma =
+                (3.0 * va + rj) * rinv2 + alpha * (3.0 * beta - 4.0 * alpha * alpha);
+            for (int d = 0; d < 3; ++d) {
+                const double A = mr3 * r[d];
+                const double J = mr3 * w[d] - 3.0 * alpha * A;
+                const double S = mr3 * q[d] - 6.0 * alpha * J - 3.0 * beta * A;
+                const double Cc = mr3 * u[d] - 9.0 * alpha * S - 9.0 * beta * J -
+                                  3.0 * gamma * A;
+                ai[d] += A;
+                ji[d] += J;
+                si[d] += S;
+                ci[d] += Cc;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            acc[3 * k + d] = ai[d];
+            jrk[3 * k + d] = ji[d];
+            snp[3 * k + d] = si[d];
+            crk[3 * k + d] = ci[d];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* O2. Prediction step (paper Sect. 3, item 1): Taylor series of      */
 /* position to the crackle term, velocity to the crackle term and     */
 /* acceleration to the crackle term.                                  */
@@ -325,10 +390,12 @@ int orc_correct(orc_state *st, int64_t n_act, const int64_t *idx, double t_new,
 /* ------------------------------------------------------------------ */
 /* O7. Initialization (the paper does not describe it).  READING:     */
 /* pass 1 evaluates a and da with zero source accelerations (they do  */
-/* not enter a or da); pass 2 repeats the evaluation with the pass-1  */
-/* accelerations as the sources' a_j, which gives d2a.  Crackle       */
-/* starts at zero, t_i = 0, and the first step is the power of two    */
-/* below eta_init |a| / |da|, with the block rules applied.           */
+/* not enter a or da); pass 2 evaluates d2a and the crackle with the  */
+/* pass-1 accelerations and jerks as the sources' values (O1').  With */
+/* every derivative up to the crackle known, the first step is the    */
+/* paper's generalized criterion (Eqs. indtstp, As) at the order the   */
+/* known derivatives allow, p = 4: dt = eta_init A(1) / A(2), with     */
+/* A(2) = sqrt(|da||a(3)| + |d2a|^2), then the block rules; t_i = 0.   */
 /* Sources are the particles of the particle's own cluster, given by  */
 /* offsets[0..n_clusters] (pairs across clusters do not interact).    */
 /* ------------------------------------------------------------------ */
@@ -346,9 +413,10 @@ static int64_t cluster_of(int64_t i, int64_t nc, const int64_t *off)
 }
 
 static void force_clusters(orc_state *st, const double *x, const double *v,
-                           const double *a, int64_t n_act, const int64_t *idx,
-                           int64_t nc, const int64_t *off, double *acc,
-                           double *jrk, double *snp, double *pot)
+                           const double *a, const double *jk, int64_t n_act,
+                           const int64_t *idx, int64_t nc, const int64_t *off,
+                           double *acc, double *jrk, double *snp, double *pot,
+                           double *crk)
 {
     /* active lists are ascending, so each cluster's actives are contiguous */
     int64_t k = 0;
@@ -357,8 +425,13 @@ static void force_clusters(orc_state *st, const double *x, const double *v,
         int64_t k1 = k;
         while (k1 < n_act && idx[k1] < off[c + 1])
             ++k1;
-        orc_force(st->n, st->m, x, v, a, st->eps, off[c], off[c + 1], k1 - k,
-                  idx + k, acc + 3 * k, jrk + 3 * k, snp + 3 * k, pot + k);
+        if (crk)
+            orc_force4(st->n, st->m, x, v, a, jk, st->eps, off[c], off[c + 1],
+                       k1 - k, idx + k, acc + 3 * k, jrk + 3 * k, snp + 3 * k,
+                       crk + 3 * k);
+        else
+            orc_force(st->n, st->m, x, v, a, st->eps, off[c], off[c + 1], k1 - k,
+                      idx + k, acc + 3 * k, jrk + 3 * k, snp + 3 * k, pot + k);
         k = k1;
     }
 }
@@ -375,17 +448,26 @@ int orc_init(orc_state *st, int64_t nc, const int64_t *off, double t_target)
     }
     for (int64_t i = 0; i < n; ++i)
         all[i] = i;
-    force_clusters(st, st->x, st->v, zero, n, all, nc, off, st->a, st->jk,
-                   st->sn, pot);
-    force_clusters(st, st->x, st->v, st->a, n, all, nc, off, st->a, st->jk,
-                   st->sn, pot);
+    force_clusters(st, st->x, st->v, zero, zero, n, all, nc, off, st->a, st->jk,
+                   st->sn, pot, NULL);
+    double *a1 = (double *)malloc(sizeof(double) * (size_t)(6 * n));
+    if (!a1) {
+        free(all); free(zero); free(pot);
+        return ORC_EINVAL;
+    }
+    memcpy(a1, st->a, sizeof(double) * (size_t)(3 * n));
+    memcpy(a1 + 3 * n, st->jk, sizeof(double) * (size_t)(3 * n));
+    force_clusters(st, st->x, st->v, a1, a1 + 3 * n, n, all, nc, off, st->a,
+                   st->jk, st->sn, pot, st->cr);
+    free(a1);
     int err = ORC_OK;
     for (int64_t i = 0; i < n; ++i) {
-        for (int d = 0; d < 3; ++d)
-            st->cr[3 * i + d] = 0.0;
         st->t[i] = 0.0;
-        const double na = norm3(st->a + 3 * i), nj = norm3(st->jk + 3 * i);
-        const double dtc = (nj > 0.0) ? st->eta_init * na / nj : INFINITY;
+        const double A1 = sqrt(norm3(st->a + 3 * i) * norm3(st->sn + 3 * i) +
+                               norm3(st->jk + 3 * i) * norm3(st->jk + 3 * i));
+        const double A2 = sqrt(norm3(st->jk + 3 * i) * norm3(st->cr + 3 * i) +
+                               norm3(st->sn + 3 * i) * norm3(st->sn + 3 * i));
+        const double dtc = (A2 > 0.0) ? st->eta_init * A1 / A2 : INFINITY;
         double dtn = 0.0;
         const int e = orc_block_dt(dtc, 0.0, 0.0, t_target, st->dt_min,
                                    st->dt_max, &dtn);
@@ -442,7 +524,8 @@ int orc_block_step(orc_state *st, int64_t nc, const int64_t *off,
     if (na > 0) {
         double *acc = out, *jrk = out + 3 * na, *snp = out + 6 * na,
                *pot = out + 9 * na;
-        force_clusters(st, xp, vp, ap, na, idx, nc, off, acc, jrk, snp, pot);
+        force_clusters(st, xp, vp, ap, NULL, na, idx, nc, off, acc, jrk, snp, pot,
+                       NULL);
         /* correct each cluster's block at its own block time */
         int64_t k = 0;
         while (k < na) {

@@ -289,6 +289,48 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     return NBODY_OK;
 }
 
+// the two start-up passes over every particle (see nbody_init)
+int run_force_init(Ctx &c)
+{
+    hipStream_t s = c.stream;
+    const int64_t n = c.n;
+    HIPCHK(c, launch_segments(c, nullptr, n, s));
+    Launch L = pick_launch(c, c.nc == 1 ? n : std::max<int64_t>(1, n / c.nc), max_cluster(c));
+    L.split = 1;
+    while (n * L.lpi < (int64_t(1) << 18) && L.lpi < 64)
+        L.lpi <<= 1;
+    const int64_t ib = iblock_size(L);
+    ForceWork w{};
+    w.seg = c.d_seg;
+    w.off = c.d_off;
+    w.split = 1;
+    w.nc = c.nc;
+    if (c.nc == 1) {
+        w.n_blocks = (n + ib - 1) / ib;
+    } else {
+        const int64_t cap = n / ib + c.nc + 1;
+        HIPCHK(c, launch_blocks(c, ib, cap, s));
+        w.blk_cluster = c.d_blk_cluster;
+        w.blk_first = c.d_blk_first;
+        w.n_blocks = cap;
+    }
+    ForceOut o1{};
+    o1.vec[0] = c.fnew;
+    o1.vec[1] = c.fnew + 3 * n;
+    o1.sk = 1;
+    o1.sd = n;
+    HIPCHK(c, launch_force_init(c, w, L, o1, s));
+    HIPCHK(c, hipMemcpyAsync(c.st.acc, c.fnew, 3 * n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c.st.jrk, c.fnew + 3 * n, 3 * n * 8, hipMemcpyDeviceToDevice, s));
+    ForceOut o2{};
+    o2.vec[2] = c.st.snp;
+    o2.vec[3] = c.st.crk;
+    o2.sk = 1;
+    o2.sd = n;
+    HIPCHK(c, launch_force_init(c, w, L, o2, s));
+    return NBODY_OK;
+}
+
 // one block step; fills n_act / t_block and adds to stats
 int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
                nbody_step_stats *stats)
@@ -353,7 +395,7 @@ void nbody_default_config(nbody_config *cfg)
         return;
     std::memset(cfg, 0, sizeof *cfg);
     cfg->eta = 0.45;
-    cfg->eta_init = 0.01;
+    cfg->eta_init = 0.1;
     cfg->dt_min = std::ldexp(1.0, -25);
     cfg->dt_max = 1.0 / 16;
     cfg->precision = NBODY_PREC_MIXED;
@@ -472,20 +514,12 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     rc = take_err(c);
     if (rc != NBODY_OK)
         return bail(rc);
-    // initialization: pass 1 (a, da with zero source accelerations), pass 2
-    // (d2a with the pass-1 accelerations); then the first steps
-    for (int pass = 0; pass < 2 && rc == NBODY_OK; ++pass) {
-        H(launch_pack(c, nullptr, 1, nullptr, s), "pack");
-        H(launch_segments(c, nullptr, n, s), "segments");
-        ForceOut fo{};
-        fo.vec[0] = c.st.acc;
-        fo.vec[1] = c.st.jrk;
-        fo.vec[2] = c.st.snp;
-        fo.sk = 1;
-        fo.sd = n;
-        if (rc == NBODY_OK)
-            rc = run_force(c, nullptr, n, c.nc == 1 ? n : std::max<int64_t>(1, n / c.nc), fo);
-    }
+    // start-up evaluation, FP64 from the stored state: pass 1 gives a and da
+    // (the sources' zero a and da do not enter them); pass 2 gives d2a and
+    // the crackle with the pass-1 values as the sources' a and da.  Then the
+    // first steps.
+    if (rc == NBODY_OK)
+        rc = run_force_init(c);
     H(launch_init_dt(c, s), "init_dt");
     if (rc == NBODY_OK)
         rc = take_err(c);

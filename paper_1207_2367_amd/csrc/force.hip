@@ -29,7 +29,7 @@ namespace nb {
 
 namespace {
 
-constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2;
+constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2, PREC_INIT = 3;
 
 // Knuth's two-sum: (hi, lo) += p without rounding loss in the (hi, lo) pair.
 __device__ __forceinline__ void ds_add(float &hi, float &lo, float p)
@@ -59,6 +59,10 @@ template <>
 struct Smem<PREC_POT> {
     using R = JRecF64;
 };
+template <>
+struct Smem<PREC_INIT> {
+    using R = JRecF64;
+};
 
 template <int PREC, int LPI, int NW, bool EPS0>
 __global__ __launch_bounds__(NW * 64) void force_kernel(
@@ -71,12 +75,15 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     constexpr int PER = NT / LPI;    // pairs per lane per tile
     constexpr bool MIXED = PREC == PREC_MIXED;
     constexpr bool POT = PREC == PREC_POT;
+    constexpr bool INIT = PREC == PREC_INIT;
+    constexpr int NV = INIT ? 12 : 9;   // vector outputs (3 components each)
     using VT = typename std::conditional<MIXED, float, double>::type;
 
     __shared__ double s_x[NT], s_y[NT], s_z[NT];
     __shared__ VT s_m[NT];
     __shared__ VT s_vx[POT ? 1 : NT], s_vy[POT ? 1 : NT], s_vz[POT ? 1 : NT];
     __shared__ VT s_ax[POT ? 1 : NT], s_ay[POT ? 1 : NT], s_az[POT ? 1 : NT];
+    __shared__ double s_jx[INIT ? NT : 1], s_jy[INIT ? NT : 1], s_jz[INIT ? NT : 1];
 
     // ---- which active slots and which sources this workgroup takes
     const int64_t g = blockIdx.x;
@@ -112,14 +119,18 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         vxi = J.vx[i]; vyi = J.vy[i]; vzi = J.vz[i];
         axi = J.ax[i]; ayi = J.ay[i]; azi = J.az[i];
     }
+    double jxi = 0, jyi = 0, jzi = 0;
+    if constexpr (INIT) {
+        jxi = J.jx[i]; jyi = J.jy[i]; jzi = J.jz[i];
+    }
     const VT e2 = (VT)eps2;
 
     // accumulators: double-single pairs (mixed) or FP64 for a, da, d2a; the
     // potential takes every FP32 pair term into an FP64 sum directly, so that
     // the large j == i term (-m_i / eps) is removed exactly at the end
-    VT A[9], L[9];
+    VT A[NV], L[NV];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < NV; ++q) {
         A[q] = 0;
         L[q] = 0;
     }
@@ -137,6 +148,9 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 s_vx[tid] = J.vx[jj]; s_vy[tid] = J.vy[jj]; s_vz[tid] = J.vz[jj];
                 s_ax[tid] = J.ax[jj]; s_ay[tid] = J.ay[jj]; s_az[tid] = J.az[jj];
             }
+            if constexpr (INIT) {
+                s_jx[tid] = J.jx[jj]; s_jy[tid] = J.jy[jj]; s_jz[tid] = J.jz[jj];
+            }
         } else {
             s_x[tid] = NULL_POS;
             s_y[tid] = NULL_POS;
@@ -146,12 +160,15 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
                 s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
             }
+            if constexpr (INIT) {
+                s_jx[tid] = 0; s_jy[tid] = 0; s_jz[tid] = 0;
+            }
         }
         __syncthreads();
 
-        VT T[9];
+        VT T[NV];
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
+        for (int q = 0; q < NV; ++q)
             T[q] = 0;
 
 #pragma unroll 4
@@ -171,7 +188,33 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 rinv = r2 > (VT)0 ? rinv : (VT)0;
             const VT mrinv = mj * rinv;
             phi -= (double)mrinv;
-            if constexpr (!POT) {
+            if constexpr (INIT) {
+                // start-up evaluation with the crackle, written term by term
+                const double dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
+                const double dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
+                const double djx = s_jx[t] - jxi, djy = s_jy[t] - jyi, djz = s_jz[t] - jzi;
+                const double rinv2 = rinv * rinv;
+                const double mr3 = mrinv * rinv2;
+                const double alpha = (dx * dvx + dy * dvy + dz * dvz) * rinv2;
+                const double beta = (dvx * dvx + dvy * dvy + dvz * dvz + dx * dax + dy * day +
+                                     dz * daz) * rinv2 + alpha * alpha;
+                const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) + dx * djx +
+                                      dy * djy + dz * djz) * rinv2 +
+                                     alpha * (3.0 * beta - 4.0 * alpha * alpha);
+                const double Ax = mr3 * dx, Ay = mr3 * dy, Az = mr3 * dz;
+                const double Jx = mr3 * dvx - 3.0 * alpha * Ax;
+                const double Jy = mr3 * dvy - 3.0 * alpha * Ay;
+                const double Jz = mr3 * dvz - 3.0 * alpha * Az;
+                const double Sx = mr3 * dax - 6.0 * alpha * Jx - 3.0 * beta * Ax;
+                const double Sy = mr3 * day - 6.0 * alpha * Jy - 3.0 * beta * Ay;
+                const double Sz = mr3 * daz - 6.0 * alpha * Jz - 3.0 * beta * Az;
+                T[0] += Ax; T[1] += Ay; T[2] += Az;
+                T[3] += Jx; T[4] += Jy; T[5] += Jz;
+                T[6] += Sx; T[7] += Sy; T[8] += Sz;
+                T[NV - 3] += mr3 * djx - 9.0 * alpha * Sx - 9.0 * beta * Jx - 3.0 * gamma * Ax;
+                T[NV - 2] += mr3 * djy - 9.0 * alpha * Sy - 9.0 * beta * Jy - 3.0 * gamma * Ay;
+                T[NV - 1] += mr3 * djz - 9.0 * alpha * Sz - 9.0 * beta * Jz - 3.0 * gamma * Az;
+            } else if constexpr (!POT) {
                 const VT dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
                 const VT dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
                 const VT rinv2 = rinv * rinv;
@@ -201,7 +244,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
             }
         }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
+        for (int q = 0; q < NV; ++q) {
             if constexpr (MIXED)
                 ds_add(A[q], L[q], T[q]);
             else
@@ -210,15 +253,15 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     }
 
     // ---- combine the LPI lanes of each active particle (xor butterfly)
-    double R[10];
+    double R[NV + 1];
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
+    for (int q = 0; q < NV; ++q)
         R[q] = MIXED ? (double)A[q] + (double)L[q] : (double)A[q];
-    R[9] = phi;
+    R[NV] = phi;
 #pragma unroll
     for (int msk = 1; msk < LPI; msk <<= 1) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q)
+        for (int q = 0; q < NV + 1; ++q)
             R[q] += __shfl_xor(R[q], msk, 64);
     }
 
@@ -234,8 +277,17 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 ri = __builtin_amdgcn_rsqf(fma((VT)0, (VT)0, fma((VT)0, (VT)0, fma((VT)0, (VT)0, e2))));
             else
                 ri = rsqrt(e2);
-            R[9] += (double)(mi * ri);
+            R[NV] += (double)(mi * ri);
         }
+    }
+    if constexpr (INIT) {
+#pragma unroll
+        for (int q = 0; q < NV / 3; ++q)
+            if (out.vec[q])
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
+        return;
     }
     if (part) {
         double *pb = part + (int64_t)b * 10 * n_act_total + k;
@@ -251,7 +303,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                     out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
         }
         if (out.pot)
-            out.pot[k] = R[9];
+            out.pot[k] = R[NV];
     }
 }
 
@@ -290,10 +342,10 @@ using KMixed = void (*)(JRecMixed, ForceWork, ForceOut, double *, int64_t, doubl
 using KF64 = void (*)(JRecF64, ForceWork, ForceOut, double *, int64_t, double);
 
 template <int PREC, bool EPS0, int NW>
-constexpr auto pick_lpi(int lpi_log2)
+auto pick_lpi(int lpi_log2)
 {
     using K = typename std::conditional<PREC == PREC_MIXED, KMixed, KF64>::type;
-    constexpr K tab[7] = {
+    static const K tab[7] = {
         force_kernel<PREC, 1, NW, EPS0>,  force_kernel<PREC, 2, NW, EPS0>,
         force_kernel<PREC, 4, NW, EPS0>,  force_kernel<PREC, 8, NW, EPS0>,
         force_kernel<PREC, 16, NW, EPS0>, force_kernel<PREC, 32, NW, EPS0>,
@@ -404,6 +456,27 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
                        w.split, n_act_total, out, prec == PREC_POT ? 1 : 0);
     prof_end(c, rr);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_init(Ctx &c, const ForceWork &w, const Launch &L,
+                             const ForceOut &out, hipStream_t s)
+{
+    if (w.n_blocks <= 0)
+        return hipSuccess;
+    JRecF64 J{};
+    J.x = c.st.pos; J.y = c.st.pos + c.n; J.z = c.st.pos + 2 * c.n;
+    J.vx = c.st.vel; J.vy = c.st.vel + c.n; J.vz = c.st.vel + 2 * c.n;
+    J.ax = c.st.acc; J.ay = c.st.acc + c.n; J.az = c.st.acc + 2 * c.n;
+    J.jx = c.st.jrk; J.jy = c.st.jrk + c.n; J.jz = c.st.jrk + 2 * c.n;
+    J.m = c.st.mass;
+    ForceWork w1 = w;
+    w1.split = 1;
+    const int lg = ilog2(L.lpi);
+    KF64 k = c.eps == 0.0 ? pick_kernel<PREC_INIT, true>(lg, L.waves)
+                          : pick_kernel<PREC_INIT, false>(lg, L.waves);
+    hipLaunchKernelGGL(k, dim3((unsigned)w1.n_blocks, 1), dim3(64 * L.waves), 0, s, J, w1, out,
+                       (double *)nullptr, (int64_t)0, c.eps * c.eps);
     return hipGetLastError();
 }
 

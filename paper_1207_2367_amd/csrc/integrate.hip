@@ -420,7 +420,8 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
         atomicOr(err, bad);
 }
 
-// first step after initialization: eta_init |a| / |da|
+// first step after the start-up evaluation: the generalized criterion at
+// the order the known derivatives allow (p = 4), eta_init A(1) / A(2)
 __global__ __launch_bounds__(TPB) void init_dt_kernel(State st, int64_t n, double eta_init,
                                                       double dt_min, double dt_max,
                                                       uint32_t *err)
@@ -430,14 +431,15 @@ __global__ __launch_bounds__(TPB) void init_dt_kernel(State st, int64_t n, doubl
         return;
     const double na = norm3(st.acc[i], st.acc[n + i], st.acc[2 * n + i]);
     const double nj = norm3(st.jrk[i], st.jrk[n + i], st.jrk[2 * n + i]);
-    const double crit = nj > 0.0 ? eta_init * na / nj : INFINITY;
+    const double ns = norm3(st.snp[i], st.snp[n + i], st.snp[2 * n + i]);
+    const double nc = norm3(st.crk[i], st.crk[n + i], st.crk[2 * n + i]);
+    const double A1 = sqrt(na * ns + nj * nj);
+    const double A2 = sqrt(nj * nc + ns * ns);
+    const double crit = A2 > 0.0 ? eta_init * A1 / A2 : INFINITY;
     double dt = dt_max;
     const uint32_t bad = block_dt(crit, 0.0, 0.0, INFINITY, dt_min, dt_max, &dt);
     st.dt[i] = dt;
     st.t[i] = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        st.crk[(int64_t)d * n + i] = 0.0;
     if (bad)
         atomicOr(err, bad);
 }

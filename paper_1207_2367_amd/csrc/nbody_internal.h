@@ -24,6 +24,7 @@ struct JRecMixed {
 };
 struct JRecF64 {
     double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *m;
+    double *jx, *jy, *jz;   // sources' jerks: start-up evaluation only
 };
 
 // Hermite state, FP64 structure-of-arrays: component d of particle i of
@@ -34,10 +35,11 @@ struct State {
 };
 
 // Where a force evaluation writes: component d of output q (0 acc, 1 jrk,
-// 2 snp) of active slot k goes to vec[q][k * sk + d * sd]; the potential to
-// pot[k] (pot may be null).
+// 2 snp, 3 crackle -- start-up evaluation only) of active slot k goes to
+// vec[q][k * sk + d * sd]; the potential to pot[k].  A null vec[q] or pot
+// is not written.
 struct ForceOut {
-    double *vec[3];
+    double *vec[4];
     double *pot;
     int64_t sk, sd;
 };
@@ -68,6 +70,10 @@ struct Ctx;
 hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
                         const ForceOut &out, int64_t n_act_total, hipStream_t s);
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
+// start-up evaluation (FP64, a, da, d2a and crackle of every particle from
+// the stored state): split = 1, results written straight to out
+hipError_t launch_force_init(Ctx &c, const ForceWork &w, const Launch &L,
+                             const ForceOut &out, hipStream_t s);
 int64_t iblock_size(const Launch &L);
 
 // integrate.hip

@@ -139,7 +139,7 @@ def _dev_i32(t, device):
 class System:
     """One N-body system (or ensemble of clusters) resident on the GPU."""
 
-    def __init__(self, mass, pos, vel, eps, *, eta=0.45, eta_init=0.01,
+    def __init__(self, mass, pos, vel, eps, *, eta=0.45, eta_init=0.1,
                  dt_min=2.0 ** -25, dt_max=1.0 / 16, precision=PREC_MIXED,
                  offsets=None, validate=False, device="cuda"):
         lib = load()

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(lib):
 def test_default_config_and_workspace_size(lib):
     from paper_1207_2367_amd import nbody
     cfg = nbody.default_config()
-    assert cfg.eta == 0.45 and cfg.eta_init == 0.01
+    assert cfg.eta == 0.45 and cfg.eta_init == 0.1
     assert cfg.dt_min == 2.0 ** -25 and cfg.dt_max == 1.0 / 16
     assert cfg.precision == nbody.PREC_MIXED and cfg.n_clusters == 1
     ws = nbody.workspace_bytes(65536, cfg)

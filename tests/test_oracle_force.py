@@ -119,6 +119,63 @@ def test_softened_terms_are_time_derivatives_of_the_potential_gradient():
                 assert abs(got[i, d] - float(ref)) < 1e-12 * (1 + abs(float(ref))), (i, d, k)
 
 
+def test_crackle_is_third_time_derivative_of_the_potential_gradient():
+    """The start-up evaluation's crackle (and its a, da, d2a) equal minus the
+    gradient of the softened potential and its first three time derivatives
+    along cubic trajectories r_k(t) = x + v t + a t^2/2 + j t^3/6, taken
+    numerically by mpmath from the potential alone."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(23)
+    n = 4
+    x = rng.normal(0, 0.3, (n, 3))
+    v = rng.normal(0, 0.5, (n, 3))
+    a = rng.normal(0, 0.8, (n, 3))
+    jk = rng.normal(0, 1.5, (n, 3))
+    m = rng.uniform(0.1, 1.0, n)
+    eps = 0.05
+    acc, jrk, snp, crk = oracle.force4(m, x, v, a, jk, eps)
+    ref3 = oracle.force(m, x, v, a, eps)
+    for got, ref in zip((acc, jrk, snp), ref3[:3]):
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+    X, V, A, Jk = ([[mp.mpf(q) for q in row] for row in arr] for arr in (x, v, a, jk))
+    for i in (1, 2):
+        def phi(dx, dy, dz, t):
+            tot = mp.mpf(0)
+            def traj(k, d):
+                return X[k][d] + V[k][d] * t + A[k][d] * t ** 2 / 2 + Jk[k][d] * t ** 3 / 6
+            ri = [traj(i, d) + (dx, dy, dz)[d] for d in range(3)]
+            for j in range(n):
+                if j == i:
+                    continue
+                s2 = sum((traj(j, d) - ri[d]) ** 2 for d in range(3)) + mp.mpf(eps) ** 2
+                tot -= mp.mpf(m[j]) / mp.sqrt(s2)
+            return tot
+        for d in range(3):
+            order = [0, 0, 0, 3]
+            order[d] = 1
+            ref = -mp.diff(phi, (0, 0, 0, 0), tuple(order))
+            assert abs(crk[i, d] - float(ref)) < 1e-11 * (1 + abs(float(ref))), (i, d)
+
+
+def test_circular_binary_crackle_and_first_step():
+    """Circular binary: crackle = w^4 v (kinematics), and the start-up step
+    criterion with p = 4 gives eta_init A(1)/A(2) = eta_init / w, rounded
+    down to a power of two."""
+    m1, m2, R = 0.3, 0.7, 0.5
+    M = m1 + m2
+    w = math.sqrt(M / R ** 3)
+    u, ut = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    x = np.array([-(m2 / M) * R * u, (m1 / M) * R * u])
+    v = np.array([-(m2 / M) * R * w * ut, (m1 / M) * R * w * ut])
+    acc, jrk, snp, crk = oracle.force4(np.array([m1, m2]), x, v, -w * w * x, -w * w * v, 0.0)
+    np.testing.assert_allclose(crk, w ** 4 * v, rtol=1e-13, atol=1e-13 * w ** 4 * R)
+    it = oracle.Integrator(np.array([m1, m2]), x, v, 0.0, eta_init=0.2, dt_min=2.0 ** -30, dt_max=1.0)
+    assert it.init(math.inf) == 0
+    np.testing.assert_allclose(it.cr, w ** 4 * v, rtol=1e-12, atol=1e-12 * w ** 4 * R)
+    want = 2.0 ** math.floor(math.log2(0.2 / w))
+    assert np.all(it.dt == want)
+
+
 # ---------------------------------------------------------- invariants
 def _plummer_inputs(n, seed):
     m, x, v = ics.plummer(n, seed)

@@ -20,6 +20,10 @@ MUTANTS = [
      "const double alpha = rv / (r2 - eps2 + 1e-300);"),
     ("acc_transposed_r", "r[d] = x[3 * j + d] - x[3 * i + d];", "r[d] = x[3 * i + d] - x[3 * j + d];"),
     ("pot_self_term", "if (j == i)\n                continue;", "if (0)\n                continue;"),
+    ("crackle_9beta", "- 9.0 * beta * J", "- 6.0 * beta * J"),
+    ("crackle_gamma_4alpha3", "(3.0 * beta - 4.0 * alpha * alpha)", "(3.0 * beta - 3.0 * alpha * alpha)"),
+    ("crackle_gamma_3va", "(3.0 * va + rj) * rinv2", "(va + rj) * rinv2"),
+    ("init_step_order", "st->eta_init * A1 / A2", "st->eta_init * sqrt(A1 / A2)"),
     ("predict_h4", "sn[e] * h4 / 24.0 + cr[e] * h5 / 120.0", "sn[e] * h4 / 12.0 + cr[e] * h5 / 120.0"),
     ("predict_vel_crackle", "cr[e] * h4 / 24.0;", "cr[e] * h4 / 6.0;"),
     ("corrector_h2", "h * h / 10.0 * (j1[d] - j0[d])", "h * h / 12.0 * (j1[d] - j0[d])"),
