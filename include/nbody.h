@@ -58,7 +58,10 @@ typedef struct nbody_config {
     const int64_t *cluster_offsets;
     void *stream;       /* hipStream_t                                    */
     int32_t validate;   /* nonzero: nbody_force checks its index list     */
-    int32_t reserved;
+    /* nonzero: nbody_init only copies the inputs (acceleration and higher
+       derivatives zero, t = 0, dt = dt_max); the caller then provides the
+       Hermite state with nbody_set_state.                                */
+    int32_t skip_startup;
 } nbody_config;
 
 typedef struct nbody_ctx nbody_ctx;
@@ -184,8 +187,10 @@ int nbody_set_state(nbody_ctx *ctx, const double *d_pos, const double *d_vel,
 int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3]);
 
 /* Measure launch shapes of the force kernel for active-set sizes
-   1, 2, 4, ... up to n and keep the fastest for each size range in the
-   context (the autotuner).  max_ms bounds the time spent per size.
+   1, 2, 4, ... up to the largest cluster (sizes whose single launch would
+   exceed ~2^35 pairs keep the heuristic shape) and keep the fastest for
+   each size range in the context (the autotuner).  max_ms bounds the time
+   spent per size.  Uses the stored state as sources; does not change it.
    Synchronizes.  Errors: EDEVICE.                                       */
 int nbody_autotune(nbody_ctx *ctx, double max_ms);
 

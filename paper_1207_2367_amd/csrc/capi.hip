@@ -518,9 +518,13 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     // (the sources' zero a and da do not enter them); pass 2 gives d2a and
     // the crackle with the pass-1 values as the sources' a and da.  Then the
     // first steps.
-    if (rc == NBODY_OK)
-        rc = run_force_init(c);
-    H(launch_init_dt(c, s), "init_dt");
+    if (!cfg->skip_startup) {
+        if (rc == NBODY_OK)
+            rc = run_force_init(c);
+        H(launch_init_dt(c, s), "init_dt");
+    } else {
+        H(launch_init_dt(c, s), "init_dt");   // zero derivatives: dt = dt_max
+    }
     if (rc == NBODY_OK)
         rc = take_err(c);
     if (rc != NBODY_OK)
@@ -787,7 +791,10 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
     std::vector<Launch> table;
     int rc = NBODY_OK;
     std::vector<int32_t> hidx;
-    for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc; ++b) {
+    // sizes whose single launch stays below ~2^35 pairs (tens of ms); larger
+    // active sets keep the heuristic shape, which is then saturating anyway
+    for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc &&
+                    (int64_t(1) << b) * nsrc <= (int64_t(1) << 35); ++b) {
         const int64_t na = int64_t(1) << b;
         // evenly spread active particles of the first cluster
         hidx.resize(na);

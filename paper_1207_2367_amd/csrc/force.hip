@@ -20,6 +20,7 @@
 //     potential terms (all of one sign) go straight into an FP64 sum;
 //   - the LPI lanes of a particle are combined by a xor butterfly of wave
 //     shuffles (bitwise identical on every lane, fixed order);
+//   - the energy variant (PREC_POT) sums m_j / r over j > i only, FP64;
 //   - grid.y = B splits the sources; partial results go to a [B][10][n_act]
 //     buffer that a second kernel sums in fixed order b = 0 .. B-1, so the
 //     result does not depend on scheduling (no float atomics anywhere).
@@ -136,7 +137,17 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     }
     double phi = 0.0;
 
-    for (int64_t t0 = j0; t0 < j1; t0 += NT) {
+    // energy pass: only pairs j > i (the index list is the identity there),
+    // so tiles entirely at or below the workgroup's first particle are skipped
+    int64_t t_first = j0;
+    int64_t i_lo = 0, i_hi = 0;
+    if constexpr (POT) {
+        i_lo = kb;
+        i_hi = (kb + IB < s1 ? kb + IB : s1) - 1;
+        if (i_lo + 1 > j0)
+            t_first = j0 + (i_lo + 1 - j0) / NT * NT;
+    }
+    for (int64_t t0 = t_first; t0 < j1; t0 += NT) {
         __syncthreads();
         const int64_t jj = t0 + tid;
         if (jj < j1) {
@@ -186,6 +197,10 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 rinv = rsqrt(r2);
             if constexpr (EPS0)
                 rinv = r2 > (VT)0 ? rinv : (VT)0;
+            if constexpr (POT) {
+                if (t0 <= i_hi)   // a tile that may hold j <= i (uniform test)
+                    rinv = t0 + t > i ? rinv : (VT)0;
+            }
             const VT mrinv = mj * rinv;
             phi -= (double)mrinv;
             if constexpr (INIT) {
@@ -269,7 +284,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         return;
     // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
     // potential: remove that term (computed the same way) when i was a source
-    if constexpr (!EPS0) {
+    if constexpr (!EPS0 && !POT) {
         if (i >= j0 && i < j1) {
             const VT mi = J.m[i];
             VT ri;

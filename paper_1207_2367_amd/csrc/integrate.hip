@@ -466,8 +466,8 @@ __global__ __launch_bounds__(TPB) void recap_kernel(State st, int64_t n, double 
 }
 
 // ------------------------------------------------------------- energy
-// per-workgroup partial sums of E_kin, (1/2) sum m phi, L; then one
-// workgroup adds the partials in order
+// per-workgroup partial sums of E_kin, sum_i m_i phi_i (phi_i over j > i,
+// so each pair once), L; then one workgroup adds the partials in order
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
 #pragma unroll
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(TPB) void energy_partial(State st, int64_t n, const
         const double x = st.pos[i], y = st.pos[n + i], z = st.pos[2 * n + i];
         const double vx = st.vel[i], vy = st.vel[n + i], vz = st.vel[2 * n + i];
         q[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
-        q[1] = 0.5 * m * phi[i];
+        q[1] = m * phi[i];   // phi[i] = -sum_{j > i} m_j / r_ij
         q[2] = m * (y * vz - z * vy);
         q[3] = m * (z * vx - x * vz);
         q[4] = m * (x * vy - y * vx);

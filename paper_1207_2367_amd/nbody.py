@@ -32,7 +32,7 @@ class Config(C.Structure):
         ("eta", C.c_double), ("eta_init", C.c_double), ("dt_min", C.c_double),
         ("dt_max", C.c_double), ("precision", C.c_int32), ("n_clusters", C.c_int32),
         ("cluster_offsets", C.POINTER(C.c_int64)), ("stream", C.c_void_p),
-        ("validate", C.c_int32), ("reserved", C.c_int32),
+        ("validate", C.c_int32), ("skip_startup", C.c_int32),
     ]
 
 
@@ -141,7 +141,7 @@ class System:
 
     def __init__(self, mass, pos, vel, eps, *, eta=0.45, eta_init=0.1,
                  dt_min=2.0 ** -25, dt_max=1.0 / 16, precision=PREC_MIXED,
-                 offsets=None, validate=False, device="cuda"):
+                 offsets=None, validate=False, skip_startup=False, device="cuda"):
         lib = load()
         self.device = torch.device(device)
         mass = _dev_f64(mass, (-1,), self.device)
@@ -150,7 +150,8 @@ class System:
         vel = _dev_f64(vel, (n, 3), self.device)
         self._offsets = None
         cfg = default_config(eta=eta, eta_init=eta_init, dt_min=dt_min, dt_max=dt_max,
-                             precision=precision, validate=1 if validate else 0)
+                             precision=precision, validate=1 if validate else 0,
+                             skip_startup=1 if skip_startup else 0)
         if offsets is not None and len(offsets) > 2:
             self._offsets = (C.c_int64 * len(offsets))(*[int(o) for o in offsets])
             cfg.n_clusters = len(offsets) - 1
@@ -243,7 +244,10 @@ class System:
         vec = [None if q is None else _dev_f64(q, (n, 3), self.device) for q in (x, v, a, jk, sn, cr)]
         sc = [None if q is None else _dev_f64(q, (n,), self.device) for q in (t, dt)]
         self._check(load().nbody_set_state(self.ctx, *[_ptr(q) for q in vec + sc]))
-        torch.cuda.synchronize(self.device)
+        # the copies are queued on the context's stream; keep any temporaries
+        # alive until the next call (later work on that stream is ordered
+        # after the copies, so the caching allocator may reuse them safely)
+        self._keep = vec + sc
 
     def energy(self):
         ek, ep, L = C.c_double(0), C.c_double(0), (C.c_double * 3)()

@@ -1,0 +1,279 @@
+"""Runs of the five workload configurations of the hot path on one GPU with
+their checks against the FP64 oracle, each printing one JSON line (the
+measured numbers quoted in the design notes; bench.py is the timed
+benchmark).  Test infrastructure: not collected by pytest, run by hand:
+
+    python tests/scenarios.py plummer1k      # 1024-body sphere to t = 1
+    python tests/scenarios.py force64k       # force microbenchmark errors
+    python tests/scenarios.py plummer1m      # 1M bodies to t = 0.125
+    python tests/scenarios.py king256        # 256 King clusters to t = 1
+    python tests/scenarios.py plummer8m      # 8M sources x 65,536 active
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+GROUPS = [(1, 20, "A"), (21, 100, "B"), (101, 1000, "C"), (1001, 10000, "D"),
+          (10001, 100000, "E"), (100001, 1 << 40, "F")]
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _rel_rows(g, r):
+    g, r = np.asarray(g), np.asarray(r)
+    if g.ndim == 1:
+        return np.abs(g - r) / np.abs(r)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+
+
+def _err_stats(e):
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)),
+            "median": float(np.median(e)), "frac_le_1e-6": float((e <= 1e-6).mean())}
+
+
+def _run(system, t_end, profile=True):
+    if profile:
+        system.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = system.step(t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = system.profile(False) if profile else None
+    return st, wall, prof
+
+
+def plummer1k():
+    """1024-body Plummer sphere, eps 1e-4, eta 0.45, dt_max 1/16, to t = 1:
+    oracle, GPU FP64 and GPU mixed."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    m, x, v = ics.plummer(1024, 1001)
+    it = oracle.Integrator(m, x, v, 1e-4)
+    it.init(1.0)
+    e0 = sum(it.energy()[:2])
+    L0 = np.linalg.norm(it.energy()[2])
+    t0 = time.perf_counter()
+    it.run(1.0 / 16)
+    x16 = it.x.copy()
+    err, steps, pairs, hist = it.run(1.0)
+    t_or = time.perf_counter() - t0
+    res = {"config": "plummer1k", "oracle": {
+        "dE_over_E": (sum(it.energy()[:2]) - e0) / e0,
+        "dL_over_L": (np.linalg.norm(it.energy()[2]) - L0) / L0,
+        "wall_s": t_or, "cores": len(os.sched_getaffinity(0))}}
+    for name, prec in (("gpu_fp64", PREC_FP64), ("gpu_mixed", PREC_MIXED)):
+        s = System(m, x, v, 1e-4, precision=prec)
+        g0 = sum(s.energy()[:2])
+        gL0 = np.linalg.norm(s.energy()[2])
+        st16, _, _ = _run(s, 1.0 / 16, profile=False)
+        dx16 = float(np.abs(s.get_state()["x"].cpu().numpy() - x16).max())
+        st, wall, prof = _run(s, 1.0)
+        ek, ep, L = s.energy()
+        res[name] = {"dE_over_E": (ek + ep - g0) / g0,
+                     "dL_over_L": (np.linalg.norm(L) - gL0) / gL0,
+                     "block_steps": st16["block_steps"] + st["block_steps"],
+                     "max_dx_vs_oracle_t1_16": dx16, "wall_s_1_16_to_1": wall,
+                     "interactions": st16["interactions"] + st["interactions"]}
+    return res
+
+
+def force64k():
+    """Force microbenchmark: N = 65,536 (seed 2002), active subsets of
+    sizes 1 .. 65,536 (seed 2003), per-particle errors of both paths against
+    the oracle (all particles for N_act <= 8192, 1024 sampled otherwise)."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    n = 65536
+    m, x, v = ics.plummer(n, 2002)
+    a = ics.plummer_mean_acc(x)
+    rng = np.random.default_rng(2003)
+    res = {"config": "force64k", "n": n, "cases": []}
+    systems = {}
+    for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
+        s = System(m, x, v, 1e-4, precision=prec)
+        s.set_state(x=x, v=v, a=a, t=np.zeros(n), dt=np.full(n, 1.0 / 16))
+        systems[name] = s
+    for na in (1, 64, 1024, 8192, 65536):
+        idx = np.sort(rng.choice(n, na, replace=False))
+        chk = np.arange(na) if na <= 8192 else np.sort(np.random.default_rng(7).choice(na, 1024, replace=False))
+        ref = oracle.force(m, x, v, a, 1e-4, idx[chk])
+        case = {"n_act": na}
+        for name, s in systems.items():
+            got = [q.cpu().numpy() for q in s.force(idx)]
+            case[name] = {q: _err_stats(_rel_rows(g[chk], r))
+                          for q, g, r in zip(("acc", "jrk", "snp", "pot"), got, ref)}
+        res["cases"].append(case)
+        _log(f"force64k n_act {na} done")
+    return res
+
+
+def _hist_groups(hist):
+    """Per-block N_act log2 histogram -> the paper's Fig. 7 groups (approx.,
+    by the bin's lower edge)."""
+    out = {g: 0 for _, _, g in GROUPS}
+    for b, c in enumerate(hist):
+        lo = 1 << b
+        for a, z, g in GROUPS:
+            if a <= lo <= z:
+                out[g] += c
+    return out
+
+
+def plummer1m(t_end=0.125, n=1 << 20):
+    """1M-body Plummer sphere (seed 3003), eps 1e-4, eta 0.45, to t = 0.125:
+    mixed and FP64 paths, energy error, block N_act histogram, throughput,
+    per-phase time; sampled forces checked against the oracle at t = 0."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    m, x, v = ics.plummer(n, 3003)
+    res = {"config": "plummer1m", "n": n, "t_end": t_end}
+    a0 = None
+    for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
+        t0 = time.perf_counter()
+        s = System(m, x, v, 1e-4, precision=prec)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        if a0 is None:
+            a0 = s.get_state()["a"].cpu().numpy()
+        if name == "mixed":
+            # sampled check of the evaluation at t = 0 (stored state = sources)
+            smp = ics.active_subset(n, 256, 31)
+            got = [q.cpu().numpy() for q in s.force(smp)]
+            ref = oracle.force(m, x, v, a0, 1e-4, smp)
+            res["force_check_t0"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
+                                     zip(("acc", "jrk", "snp", "pot"), got, ref)}
+        e0 = sum(s.energy()[:2])
+        st, wall, prof = _run(s, t_end)
+        e1 = sum(s.energy()[:2])
+        res[name] = {"dE_over_E": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                     "interactions": st["interactions"], "wall_s": wall, "init_s": t_init,
+                     "G_interactions_per_s": st["interactions"] / wall / 1e9,
+                     "phase_ms": {k: v[0] for k, v in prof.items() if k != "pairs"},
+                     "n_act_log2_hist": st["hist"][:24],
+                     "groups": _hist_groups(st["hist"])}
+        _log(f"plummer1m {name}: {json.dumps(res[name])[:300]}")
+        del s
+        torch.cuda.empty_cache()
+    return res
+
+
+def king256(t_end=1.0):
+    """256 King W0 = 6 clusters (Kroupa-like masses), all advanced together in
+    one context to t = 1; 12 clusters also integrated by the oracle."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import PREC_MIXED, System
+    m, x, v, off = ics.king_ensemble()
+    n = m.size
+    sizes = np.diff(off)
+    res = {"config": "king256", "n_total": int(n), "clusters": int(sizes.size)}
+    t0 = time.perf_counter()
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED, offsets=off)
+    s.autotune(100.0)
+    torch.cuda.synchronize()
+    res["init_s"] = time.perf_counter() - t0
+    # per-cluster energies through separate contexts would cost N_c^2 each;
+    # the ensemble energy of the whole context is one call
+    e0 = sum(s.energy()[:2])
+    st, wall, prof = _run(s, t_end)
+    e1 = sum(s.energy()[:2])
+    res["mixed"] = {"dE_over_E_total": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                    "interactions": st["interactions"], "wall_s": wall,
+                    "G_interactions_per_s": st["interactions"] / wall / 1e9,
+                    "phase_ms": {k: v[0] for k, v in prof.items() if k != "pairs"}}
+    # oracle on the 8 smallest + 4 seeded-random clusters, and the GPU on
+    # the same clusters alone
+    pick = list(np.argsort(sizes)[:8]) + list(np.random.default_rng(4200).choice(sizes.size, 4, replace=False))
+    per = []
+    for c in pick:
+        sl = slice(off[c], off[c + 1])
+        it = oracle.Integrator(m[sl], x[sl], v[sl], 1e-4)
+        it.init(t_end)
+        o0 = sum(it.energy()[:2])
+        it.run(t_end)
+        o1 = sum(it.energy()[:2])
+        g = System(m[sl], x[sl], v[sl], 1e-4, precision=PREC_MIXED)
+        g0 = sum(g.energy()[:2])
+        g.step(t_end)
+        g1 = sum(g.energy()[:2])
+        per.append({"cluster": int(c), "n": int(sizes[c]), "oracle_dE_over_E": (o1 - o0) / o0,
+                    "gpu_mixed_dE_over_E": (g1 - g0) / g0})
+    res["per_cluster"] = per
+    return res
+
+
+def plummer8m(n=1 << 23, n_act=65536):
+    """8M sources x 65,536 active (seed 5005 / 5006): the mixed evaluation
+    alone (the state is the smooth-model start, no start-up passes), timed,
+    with 1024 sampled particles checked against the oracle."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import PREC_MIXED, System, nbody
+    m, x, v = ics.plummer(n, 5005)
+    a = ics.plummer_mean_acc(x)
+    cfg = nbody.default_config(precision=PREC_MIXED)
+    res = {"config": "plummer8m", "n": n, "n_act": n_act,
+           "workspace_GB": nbody.workspace_bytes(n, cfg) / 1e9}
+    # the start-up passes (two FP64 N^2 evaluations) would take minutes at
+    # this size and are not part of this measurement: skip them and set the
+    # state directly
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED, skip_startup=True)
+    s.set_state(x=x, v=v, a=a, t=np.zeros(n), dt=np.full(n, 1.0 / 16))
+    idx = ics.active_subset(n, n_act, 5006)
+    s.autotune(200.0)
+    s.force(idx)
+    torch.cuda.synchronize()
+    s.profile(True)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = s.force(idx)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    prof = s.profile(False)
+    kms = prof["force"][0] / prof["force"][1]
+    res["kernel_ms"] = kms
+    res["wall_ms"] = wall * 1e3
+    res["G_interactions_per_s_kernel"] = n * n_act / (kms * 1e-3) / 1e9
+    res["tflops_83"] = 83 * n * n_act / (kms * 1e-3) / 1e12
+    chk = np.sort(np.random.default_rng(9).choice(n_act, 1024, replace=False))
+    ref = oracle.force(m, x, v, a, 1e-4, idx[chk])
+    res["errors"] = {q: _err_stats(_rel_rows(g.cpu().numpy()[chk], r))
+                     for q, g, r in zip(("acc", "jrk", "snp", "pot"), got, ref)}
+    return res
+
+
+RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
+        "king256": king256, "plummer8m": plummer8m}
+
+
+def _default(o):
+    if isinstance(o, (np.integer,)):
+        return int(o)
+    if isinstance(o, (np.floating,)):
+        return float(o)
+    return str(o)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        _log(f"scenario {name}")
+        out = RUNS[name]()
+        print(json.dumps(out, default=_default), flush=True)
