@@ -15,8 +15,9 @@ synchronized state.
 value = force interactions (N * N_act summed over the five blocks) per
 second of wall time over the timed steps, inputs resident in HBM.
 
-Also reported: the same for the all-FP64 path and the speedup; the energy
-error of both paths on the 1024-body Plummer run to t = 1 (eta = 0.45); the
+Also reported: the same for the all-FP64 path and the FP32-pair mode and
+the speedups; the energy error of the three on the 1024-body Plummer run to
+t = 1 (eta = 0.45); the
 per-phase GPU time; the roofline of the dominant kernel (the evaluation
 kernel at N_act = N, timed with HIP events on its stream); and the CPU
 oracle timed on a bounded sample of the same step.
@@ -44,6 +45,10 @@ PAPER_FLOPS_PER_PAIR = 97      # the paper's convention (Table 2)
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
 PEAK_FP32_DATASHEET = 157.3                          # counts packed FP32
 PEAK_FP64 = 78.6
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes over `bench.py --profile-pass` (profiles/), scaled by the
+# same counters on a 1 GiB copy; None until measured for this kernel build.
+TRAFFIC = None
 
 
 def parse():
@@ -56,6 +61,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for rocprofv3 counter passes: a plain copy of a known "
+                         "size (counter calibration), then the mixed steps only")
     return ap.parse_args()
 
 
@@ -148,8 +156,8 @@ def cpu_baseline(n, seconds):
         err, na, tb = it.block_step(1.0 / 16)
         return time.perf_counter() - t0, na
 
-    dt_cal, _ = one(64)
-    rate = 64 * n / max(dt_cal, 1e-6)
+    dt_cal, _ = one(1024)
+    rate = 1024 * n / max(dt_cal, 1e-6)
     n_act = int(min(n, max(64, seconds * rate / n)))
     el, na = one(n_act)
     return {"value": round(na * n / el / 1e9, 4), "unit": "G interactions/s", "cores": cores,
@@ -159,7 +167,53 @@ def cpu_baseline(n, seconds):
                       f"{el:.1f} s, FP64 C oracle, OpenMP over active particles"}
 
 
+def summarize_profile(d):
+    """Text summary of rocprofv3 CSV output in directory d: kernel-trace
+    durations grouped by (kernel, grid size) and, when present, counter
+    values per dispatch of the evaluation kernels and of the calibration
+    copy.  Printed to stdout (the source of the files in profiles/)."""
+    import csv
+    import glob
+    import statistics
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        groups = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
+            key = (name, r.get("Grid_Size_X", ""), r.get("Grid_Size_Y", ""), r.get("Workgroup_Size_X", ""))
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            groups.setdefault(key, []).append(dur)
+        tot = sum(sum(v) for v in groups.values())
+        out.append(f"# {os.path.basename(f)}: {len(rows)} dispatches, {tot:.3f} ms total")
+        out.append("calls  total_ms   avg_ms     min_ms     max_ms   share  grid_x x grid_y (wg)  kernel")
+        for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            short = key[0].replace("(anonymous namespace)::", "").split("(")[0][:90]
+            out.append(f"{len(v):5d} {sum(v):9.3f} {statistics.mean(v):9.5f} {min(v):9.5f} "
+                       f"{max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} ({key[3]})  {short}")
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        per = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            if not ("force_kernel" in name or "copy" in name.lower() or "reduce_split" in name):
+                continue
+            key = (int(r["Dispatch_Id"]),
+                   name.replace("(anonymous namespace)::", "").split("(")[0][:70], r["Grid_Size"])
+            per.setdefault(key, {})
+            per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        out.append(f"# {os.path.basename(f)}")
+        for key in sorted(per):
+            vals = " ".join(f"{k}={v:.6g}" for k, v in sorted(per[key].items()))
+            out.append(f"dispatch {key[0]:5d} grid {key[2]:>9}  {key[1]}  {vals}")
+    print("\n".join(out))
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
+        summarize_profile(sys.argv[2])
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has "
@@ -167,11 +221,26 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED
+    from paper_1207_2367_amd import PREC_FP32PAIR, PREC_FP64, PREC_MIXED
     from paper_1207_2367_amd import nbody
     if not os.path.exists(nbody.lib_path()):
         import __graft_entry__
         __graft_entry__.build()
+
+    if args.profile_pass:
+        # calibration for the HBM counters: copy 1 GiB that is not cache
+        # resident (a second buffer is written in between), then the steps
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a).fill_(2.0)
+        c = torch.empty_like(a).fill_(3.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b, c
+        wl = Workload(args.n, PREC_MIXED, not args.no_autotune)
+        wl.run(args.steps, args.warmup)
+        torch.cuda.synchronize()
+        log("profile pass done")
+        return
 
     log(f"mixed: N={args.n}, warmup {args.warmup}, steps {args.steps}")
     wl = Workload(args.n, PREC_MIXED, not args.no_autotune)
@@ -197,18 +266,22 @@ def main():
                                         "split": launches[na][2]}}
     phases = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if k != "pairs"}
 
-    log("fp64 path")
     ks = args.fp64_steps or max(2, args.steps // 2)
-    wd = Workload(args.n, PREC_FP64, not args.no_autotune)
-    eld, profd = wd.run(ks, 1, profile=True)
-    value_f64 = wd.pairs_per_step * ks / eld / 1e9
-    na_d, _, ms_d = wd.sys.force_log()
-    avg_ms_d = float(ms_d[na_d == args.n].mean())
-    del wd
+    other = {}
+    for name, prec in (("fp64", PREC_FP64), ("fp32pair", PREC_FP32PAIR)):
+        log(f"{name} path")
+        wd = Workload(args.n, prec, not args.no_autotune)
+        eld, _ = wd.run(ks, 1, profile=True)
+        na_d, _, ms_d = wd.sys.force_log()
+        other[name] = (wd.pairs_per_step * ks / eld / 1e9, float(ms_d[na_d == args.n].mean()))
+        del wd
+    value_f64, avg_ms_d = other["fp64"]
+    value_p32, avg_ms_p = other["fp32pair"]
 
     log("energy error, 1024-body Plummer to t = 1")
     de_mixed, steps_m = energy_error(PREC_MIXED)
     de_f64, steps_d = energy_error(PREC_FP64)
+    de_p32, steps_p = energy_error(PREC_FP32PAIR)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -226,7 +299,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"Plummer N={args.n} (seed 2002), eps=1e-4, Henon units; one step = "
@@ -237,9 +310,12 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED, 2),
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4),
+            "traffic": TRAFFIC,
             "kernel": "evaluation (force) kernel, N_act = N",
             "kernel_avg_ms": round(avg_ms, 5), "flops_per_pair": FLOPS_PER_PAIR,
+            "peak_basis": "FP32 vector without packed math: 256 CU x 64 lanes x 2 flop x 2.4 GHz "
+                          "(packed FP32 is disabled in this build)",
             "frac_vs_fp32_datasheet_157.3": round(achieved / PEAK_FP32_DATASHEET, 4),
         },
         "fp64_path": {
@@ -248,10 +324,16 @@ def main():
             "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12, 3),
             "frac_fp64_peak": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12 / PEAK_FP64, 4),
         },
+        "fp32pair_path": {
+            "value": round(value_p32, 3), "unit": "G interactions/s",
+            "kernel_ms_at_N": round(avg_ms_p, 5),
+            "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (avg_ms_p * 1e-3) / 1e12, 3),
+        },
         "speedup_mixed_vs_fp64": round(value / value_f64, 3),
         "kernel_speedup_mixed_vs_fp64": round(avg_ms_d / avg_ms, 3),
-        "dE_over_E_plummer1024_t1": {"mixed": de_mixed, "fp64": de_f64,
-                                     "block_steps": [steps_m, steps_d]},
+        "kernel_speedup_fp32pair_vs_fp64": round(avg_ms_d / avg_ms_p, 3),
+        "dE_over_E_plummer1024_t1": {"mixed": de_mixed, "fp64": de_f64, "fp32pair": de_p32,
+                                     "block_steps": [steps_m, steps_d, steps_p]},
         "paper_equiv_gflops": round(value * PAPER_FLOPS_PER_PAIR, 1),
         "per_n_act": per_nact,
         "phase_ms_per_step": phases,

@@ -40,16 +40,28 @@ extern "C" {
 #define NBODY_EDTMIN (-4)     /* a particle needs a step below dt_min      */
 #define NBODY_ESTATE (-5)     /* call not valid in the context's state     */
 
-#define NBODY_PREC_MIXED 0 /* FP64 state and r_j - r_i, FP32 pair terms,
-                              compensated (double-single) accumulation     */
-#define NBODY_PREC_FP64 1  /* every operation in FP64 (comparison path)   */
+/* Precision of the evaluation (the state, predictor, corrector, step
+   criterion and energy are FP64 in every mode):
+   MIXED (default): r_j - r_i, r^2, 1/r (FP32 rsqrt seed + one FP64 Newton
+     step), the acceleration and potential terms and their sums in FP64;
+     jerk and snap terms in FP32 with compensated (double-single)
+     accumulation.  The step criterion's fifth-derivative estimate
+     amplifies the acceleration's absolute error by ~720/h^5, which with
+     FP32 acceleration terms can drive steps down to dt_min.
+   FP32PAIR: every pair term in FP32 (from the FP64 difference r_j - r_i)
+     with compensated accumulation -- fastest; safe only where steps stay
+     near their natural length.
+   FP64: every operation in FP64 (comparison path).                      */
+#define NBODY_PREC_MIXED 0
+#define NBODY_PREC_FP64 1
+#define NBODY_PREC_FP32PAIR 2
 
 typedef struct nbody_config {
     double eta;      /* accuracy parameter of the step criterion, > 0     */
     double eta_init; /* first step: eta_init A(1)/A(2) (p = 4), see init   */
     double dt_min;   /* smallest block step, a power of two               */
     double dt_max;   /* largest block step, a power of two >= dt_min      */
-    int32_t precision;  /* NBODY_PREC_MIXED or NBODY_PREC_FP64            */
+    int32_t precision;  /* NBODY_PREC_MIXED, _FP64 or _FP32PAIR           */
     int32_t n_clusters; /* 0 or 1: one system; > 1: independent clusters  */
     /* host array [n_clusters + 1], ascending, 0 ... n: particles
        [off[c], off[c+1]) form cluster c; pairs across clusters do not

@@ -8,5 +8,5 @@ tensors.  There is no CPU path: without the built library every call fails.
 """
 from .nbody import (  # noqa: F401
     NBodyError, System, default_config, lib_path, load, workspace_bytes,
-    PREC_MIXED, PREC_FP64,
+    PREC_MIXED, PREC_FP64, PREC_FP32PAIR,
 )

@@ -41,7 +41,8 @@ bool config_ok(const nbody_config *cfg, int64_t n)
         return false;
     if (!is_pow2(cfg->dt_min) || !is_pow2(cfg->dt_max) || cfg->dt_min > cfg->dt_max)
         return false;
-    if (cfg->precision != NBODY_PREC_MIXED && cfg->precision != NBODY_PREC_FP64)
+    if (cfg->precision != NBODY_PREC_MIXED && cfg->precision != NBODY_PREC_FP64 &&
+        cfg->precision != NBODY_PREC_FP32PAIR)
         return false;
     if (cfg->n_clusters > 1) {
         const int64_t *o = cfg->cluster_offsets;
@@ -129,11 +130,12 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     st.mass = (double *)take(n * d);
     JRecMixed jm{};
     JRecF64 jd{};
-    if (prec == NBODY_PREC_MIXED) {
+    if (prec != NBODY_PREC_FP64) {
         jm.x = (double *)take(n * d);
         jm.y = (double *)take(n * d);
         jm.z = (double *)take(n * d);
-        float **fl[7] = {&jm.vx, &jm.vy, &jm.vz, &jm.ax, &jm.ay, &jm.az, &jm.m};
+        jm.m = (double *)take(n * d);
+        float **fl[6] = {&jm.vx, &jm.vy, &jm.vz, &jm.ax, &jm.ay, &jm.az};
         for (auto p : fl)
             *p = (float *)take(n * f);
     } else {

@@ -13,11 +13,15 @@
 //   - the pair loop is pure vector ALU: no matrix cores, the work is not a
 //     dense contraction (every pair needs a reciprocal square root and
 //     nonlinear terms);
-//   - mixed precision: r_j - r_i in FP64, rounded to FP32, all other pair
-//     arithmetic in FP32 with v_rsq_f32; per-tile FP32 partial sums of a,
-//     da, d2a are folded into double-single (hi, lo) accumulators by an
-//     error-free two-sum, so the cross-tile sum carries ~48 bits; the
-//     potential terms (all of one sign) go straight into an FP64 sum;
+//   - mixed precision: r_j - r_i, r^2 and 1/r (v_rsq_f32 seed + one FP64
+//     Newton step) in FP64, and with them the acceleration and potential
+//     terms, summed in FP64; the jerk and snap terms in FP32 from the
+//     rounded r_j - r_i, FP32 velocity and acceleration differences, summed
+//     over at most 64 pairs per lane in FP32 and folded into double-single
+//     (hi, lo) accumulators by an error-free two-sum.  The split follows
+//     where the method amplifies errors: the fifth-derivative estimate of
+//     the step criterion multiplies the acceleration's absolute error by
+//     ~720/h^5 but the jerk's and snap's by at most ~1/h^4 and ~1/h^3;
 //   - the LPI lanes of a particle are combined by a xor butterfly of wave
 //     shuffles (bitwise identical on every lane, fixed order);
 //   - the energy variant (PREC_POT) sums m_j / r over j > i only, FP64;
@@ -30,7 +34,9 @@ namespace nb {
 
 namespace {
 
-constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2, PREC_INIT = 3;
+// kernel variants: the two public mixed modes, the FP64 path, the energy
+// pass and the start-up pass
+constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2, PREC_INIT = 3, PREC_PAIR32 = 4;
 
 // Knuth's two-sum: (hi, lo) += p without rounding loss in the (hi, lo) pair.
 __device__ __forceinline__ void ds_add(float &hi, float &lo, float p)
@@ -53,6 +59,10 @@ struct Smem<PREC_MIXED> {
     using R = JRecMixed;
 };
 template <>
+struct Smem<PREC_PAIR32> {
+    using R = JRecMixed;
+};
+template <>
 struct Smem<PREC_F64> {
     using R = JRecF64;
 };
@@ -65,6 +75,17 @@ struct Smem<PREC_INIT> {
     using R = JRecF64;
 };
 
+// 1/sqrt(r2) for the mixed path: FP32 seed from v_rsq_f32 (|error| < 1 ulp,
+// measured) and one Newton step in FP64, which squares the relative error
+// (~1e-14).  Used for the acceleration and potential terms and, with the
+// same operations, for the removal of the j == i potential term.
+__device__ __forceinline__ double rinv_mixed(double r2)
+{
+    const double y0 = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double res = fma(-r2 * y0, y0, 1.0);   // 1 - r2 y0^2
+    return fma(0.5 * y0, res, y0);
+}
+
 template <int PREC, int LPI, int NW, bool EPS0>
 __global__ __launch_bounds__(NW * 64) void force_kernel(
     typename Smem<PREC>::R J, ForceWork w, ForceOut out, double *part,
@@ -75,13 +96,17 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     constexpr int IB = NW * GI;      // active particles per workgroup
     constexpr int PER = NT / LPI;    // pairs per lane per tile
     constexpr bool MIXED = PREC == PREC_MIXED;
+    constexpr bool P32 = PREC == PREC_PAIR32;
     constexpr bool POT = PREC == PREC_POT;
     constexpr bool INIT = PREC == PREC_INIT;
     constexpr int NV = INIT ? 12 : 9;   // vector outputs (3 components each)
-    using VT = typename std::conditional<MIXED, float, double>::type;
+    // FP32 accumulators (mixed: jerk and snap; FP32-pair mode: all nine);
+    // FP64 ones for the rest
+    constexpr int NF = MIXED ? 6 : (P32 ? 9 : 1);
+    constexpr int ND = MIXED ? 3 : (P32 ? 1 : NV);
+    using VT = typename std::conditional<MIXED || P32, float, double>::type;
 
-    __shared__ double s_x[NT], s_y[NT], s_z[NT];
-    __shared__ VT s_m[NT];
+    __shared__ double s_x[NT], s_y[NT], s_z[NT], s_m[NT];
     __shared__ VT s_vx[POT ? 1 : NT], s_vy[POT ? 1 : NT], s_vz[POT ? 1 : NT];
     __shared__ VT s_ax[POT ? 1 : NT], s_ay[POT ? 1 : NT], s_az[POT ? 1 : NT];
     __shared__ double s_jx[INIT ? NT : 1], s_jy[INIT ? NT : 1], s_jz[INIT ? NT : 1];
@@ -124,25 +149,28 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     if constexpr (INIT) {
         jxi = J.jx[i]; jyi = J.jy[i]; jzi = J.jz[i];
     }
-    const VT e2 = (VT)eps2;
 
-    // accumulators: double-single pairs (mixed) or FP64 for a, da, d2a; the
-    // potential takes every FP32 pair term into an FP64 sum directly, so that
-    // the large j == i term (-m_i / eps) is removed exactly at the end
-    VT A[NV], L[NV];
+    // FP64 sums (mixed: acceleration; otherwise everything), the potential
+    // in FP64 always, and double-single (hi, lo) pairs for the mixed jerk
+    // and snap, fed by FP32 partial sums over at most FOLD pairs per lane
+    double D[ND];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        A[q] = 0;
-        L[q] = 0;
+    for (int q = 0; q < ND; ++q)
+        D[q] = 0.0;
+    float H[NF], L[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        H[q] = 0.0f;
+        L[q] = 0.0f;
     }
     double phi = 0.0;
 
     // energy pass: only pairs j > i (the index list is the identity there),
     // so tiles entirely at or below the workgroup's first particle are skipped
     int64_t t_first = j0;
-    int64_t i_lo = 0, i_hi = 0;
+    int64_t i_hi = 0;
     if constexpr (POT) {
-        i_lo = kb;
+        const int64_t i_lo = kb;
         i_hi = (kb + IB < s1 ? kb + IB : s1) - 1;
         if (i_lo + 1 > j0)
             t_first = j0 + (i_lo + 1 - j0) / NT * NT;
@@ -166,7 +194,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
             s_x[tid] = NULL_POS;
             s_y[tid] = NULL_POS;
             s_z[tid] = NULL_POS;
-            s_m[tid] = 0;
+            s_m[tid] = 0.0;
             if constexpr (!POT) {
                 s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
                 s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
@@ -177,101 +205,163 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         }
         __syncthreads();
 
-        VT T[NV];
+        // a short FP32 partial keeps its rounding small (64 pairs measured
+        // 3x better than 256 for the jerk, at ~1% more instructions)
+        constexpr int FOLD = (MIXED || P32) ? (PER < 64 ? PER : 64) : PER;
+        for (int p0 = 0; p0 < PER; p0 += FOLD) {
+            float T[NF];
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            T[q] = 0;
+            for (int q = 0; q < NF; ++q)
+                T[q] = 0.0f;
 
 #pragma unroll 4
-        for (int p = 0; p < PER; ++p) {
-            const int t = js + p * LPI;
-            const VT dx = (VT)(s_x[t] - xi);
-            const VT dy = (VT)(s_y[t] - yi);
-            const VT dz = (VT)(s_z[t] - zi);
-            const VT mj = s_m[t];
-            const VT r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
-            VT rinv;
-            if constexpr (MIXED)
-                rinv = __builtin_amdgcn_rsqf(r2);
-            else
-                rinv = rsqrt(r2);
-            if constexpr (EPS0)
-                rinv = r2 > (VT)0 ? rinv : (VT)0;
-            if constexpr (POT) {
-                if (t0 <= i_hi)   // a tile that may hold j <= i (uniform test)
-                    rinv = t0 + t > i ? rinv : (VT)0;
-            }
-            const VT mrinv = mj * rinv;
-            phi -= (double)mrinv;
-            if constexpr (INIT) {
-                // start-up evaluation with the crackle, written term by term
-                const double dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
-                const double dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
-                const double djx = s_jx[t] - jxi, djy = s_jy[t] - jyi, djz = s_jz[t] - jzi;
+            for (int p = p0; p < p0 + FOLD; ++p) {
+                const int t = js + p * LPI;
+                if constexpr (P32) {
+                    // every pair term in FP32 from the FP64 difference r_j - r_i
+                    const float dx = (float)(s_x[t] - xi), dy = (float)(s_y[t] - yi),
+                                dz = (float)(s_z[t] - zi);
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)eps2)));
+                    float rinv = __builtin_amdgcn_rsqf(r2);
+                    if constexpr (EPS0)
+                        rinv = r2 > 0.0f ? rinv : 0.0f;
+                    const float mrinv = (float)s_m[t] * rinv;
+                    phi -= (double)mrinv;
+                    const float rinv2 = rinv * rinv, mr3 = mrinv * rinv2;
+                    const float dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
+                    const float dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
+                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+                    const float qq = fmaf(dvx, dvx, fmaf(dvy, dvy, fmaf(dvz, dvz,
+                                     fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
+                    const float alpha = rv * rinv2;
+                    const float beta = fmaf(alpha, alpha, qq * rinv2);
+                    const float a3 = -3.0f * alpha, a6 = a3 + a3, b3 = -3.0f * beta;
+                    const float jx = fmaf(a3, dx, dvx), jy = fmaf(a3, dy, dvy), jz = fmaf(a3, dz, dvz);
+                    T[0] = fmaf(mr3, dx, T[0]);
+                    T[1] = fmaf(mr3, dy, T[1]);
+                    T[2] = fmaf(mr3, dz, T[2]);
+                    T[3] = fmaf(mr3, jx, T[3]);
+                    T[4] = fmaf(mr3, jy, T[4]);
+                    T[5] = fmaf(mr3, jz, T[5]);
+                    T[6] = fmaf(mr3, fmaf(a6, jx, fmaf(b3, dx, dax)), T[6]);
+                    T[7] = fmaf(mr3, fmaf(a6, jy, fmaf(b3, dy, day)), T[7]);
+                    T[8] = fmaf(mr3, fmaf(a6, jz, fmaf(b3, dz, daz)), T[8]);
+                    continue;
+                }
+                const double dxd = s_x[t] - xi, dyd = s_y[t] - yi, dzd = s_z[t] - zi;
+                const double r2 = fma(dxd, dxd, fma(dyd, dyd, fma(dzd, dzd, eps2)));
+                double rinv;
+                if constexpr (MIXED)
+                    rinv = rinv_mixed(r2);
+                else
+                    rinv = rsqrt(r2);
+                if constexpr (EPS0)
+                    rinv = r2 > 0.0 ? rinv : 0.0;
+                if constexpr (POT) {
+                    if (t0 <= i_hi)   // a tile that may hold j <= i (uniform test)
+                        rinv = t0 + t > i ? rinv : 0.0;
+                }
+                const double mrinv = s_m[t] * rinv;
+                phi -= mrinv;
+                if constexpr (POT)
+                    continue;
                 const double rinv2 = rinv * rinv;
                 const double mr3 = mrinv * rinv2;
-                const double alpha = (dx * dvx + dy * dvy + dz * dvz) * rinv2;
-                const double beta = (dvx * dvx + dvy * dvy + dvz * dvz + dx * dax + dy * day +
-                                     dz * daz) * rinv2 + alpha * alpha;
-                const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) + dx * djx +
-                                      dy * djy + dz * djz) * rinv2 +
-                                     alpha * (3.0 * beta - 4.0 * alpha * alpha);
-                const double Ax = mr3 * dx, Ay = mr3 * dy, Az = mr3 * dz;
-                const double Jx = mr3 * dvx - 3.0 * alpha * Ax;
-                const double Jy = mr3 * dvy - 3.0 * alpha * Ay;
-                const double Jz = mr3 * dvz - 3.0 * alpha * Az;
-                const double Sx = mr3 * dax - 6.0 * alpha * Jx - 3.0 * beta * Ax;
-                const double Sy = mr3 * day - 6.0 * alpha * Jy - 3.0 * beta * Ay;
-                const double Sz = mr3 * daz - 6.0 * alpha * Jz - 3.0 * beta * Az;
-                T[0] += Ax; T[1] += Ay; T[2] += Az;
-                T[3] += Jx; T[4] += Jy; T[5] += Jz;
-                T[6] += Sx; T[7] += Sy; T[8] += Sz;
-                T[NV - 3] += mr3 * djx - 9.0 * alpha * Sx - 9.0 * beta * Jx - 3.0 * gamma * Ax;
-                T[NV - 2] += mr3 * djy - 9.0 * alpha * Sy - 9.0 * beta * Jy - 3.0 * gamma * Ay;
-                T[NV - 1] += mr3 * djz - 9.0 * alpha * Sz - 9.0 * beta * Jz - 3.0 * gamma * Az;
-            } else if constexpr (!POT) {
-                const VT dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
-                const VT dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
-                const VT rinv2 = rinv * rinv;
-                const VT mr3 = mrinv * rinv2;
-                const VT rv = fma(dx, dvx, fma(dy, dvy, dz * dvz));
-                const VT qq = fma(dvx, dvx, fma(dvy, dvy, fma(dvz, dvz,
-                              fma(dx, dax, fma(dy, day, dz * daz)))));
-                const VT alpha = rv * rinv2;
-                const VT beta = fma(alpha, alpha, qq * rinv2);
-                const VT a3 = (VT)-3 * alpha;   // -3 alpha
-                const VT a6 = a3 + a3;          // -6 alpha
-                const VT b3 = (VT)-3 * beta;    // -3 beta
-                // J = mr3 (dv - 3 alpha dr); S = mr3 (da - 6 alpha jv - 3 beta dr)
-                const VT jx = fma(a3, dx, dvx), jy = fma(a3, dy, dvy), jz = fma(a3, dz, dvz);
-                const VT sx = fma(a6, jx, fma(b3, dx, dax));
-                const VT sy = fma(a6, jy, fma(b3, dy, day));
-                const VT sz = fma(a6, jz, fma(b3, dz, daz));
-                T[0] = fma(mr3, dx, T[0]);
-                T[1] = fma(mr3, dy, T[1]);
-                T[2] = fma(mr3, dz, T[2]);
-                T[3] = fma(mr3, jx, T[3]);
-                T[4] = fma(mr3, jy, T[4]);
-                T[5] = fma(mr3, jz, T[5]);
-                T[6] = fma(mr3, sx, T[6]);
-                T[7] = fma(mr3, sy, T[7]);
-                T[8] = fma(mr3, sz, T[8]);
+                if constexpr (MIXED) {
+                    // acceleration in FP64; jerk and snap in FP32:
+                    // J = m r^-3 (v - 3 alpha r), S = m r^-3 (a - 6 alpha jv - 3 beta r)
+                    D[0] = fma(mr3, dxd, D[0]);
+                    D[1] = fma(mr3, dyd, D[1]);
+                    D[2] = fma(mr3, dzd, D[2]);
+                    const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                    const float fr2 = (float)rinv2, fm3 = (float)mr3;
+                    const float dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
+                    const float dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
+                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+                    const float qq = fmaf(dvx, dvx, fmaf(dvy, dvy, fmaf(dvz, dvz,
+                                     fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
+                    const float alpha = rv * fr2;
+                    const float beta = fmaf(alpha, alpha, qq * fr2);
+                    const float a3 = -3.0f * alpha;
+                    const float a6 = a3 + a3;
+                    const float b3 = -3.0f * beta;
+                    const float jx = fmaf(a3, dx, dvx), jy = fmaf(a3, dy, dvy), jz = fmaf(a3, dz, dvz);
+                    const float sx = fmaf(a6, jx, fmaf(b3, dx, dax));
+                    const float sy = fmaf(a6, jy, fmaf(b3, dy, day));
+                    const float sz = fmaf(a6, jz, fmaf(b3, dz, daz));
+                    T[0] = fmaf(fm3, jx, T[0]);
+                    T[1] = fmaf(fm3, jy, T[1]);
+                    T[2] = fmaf(fm3, jz, T[2]);
+                    T[3] = fmaf(fm3, sx, T[3]);
+                    T[4] = fmaf(fm3, sy, T[4]);
+                    T[5] = fmaf(fm3, sz, T[5]);
+                } else {
+                    const double dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
+                    const double dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
+                    const double alpha = fma(dxd, dvx, fma(dyd, dvy, dzd * dvz)) * rinv2;
+                    const double qq = fma(dvx, dvx, fma(dvy, dvy, fma(dvz, dvz,
+                                      fma(dxd, dax, fma(dyd, day, dzd * daz)))));
+                    const double beta = fma(alpha, alpha, qq * rinv2);
+                    if constexpr (INIT) {
+                        // start-up evaluation with the crackle, term by term
+                        const double djx = s_jx[t] - jxi, djy = s_jy[t] - jyi, djz = s_jz[t] - jzi;
+                        const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) +
+                                              dxd * djx + dyd * djy + dzd * djz) * rinv2 +
+                                             alpha * (3.0 * beta - 4.0 * alpha * alpha);
+                        const double Ax = mr3 * dxd, Ay = mr3 * dyd, Az = mr3 * dzd;
+                        const double Jx = mr3 * dvx - 3.0 * alpha * Ax;
+                        const double Jy = mr3 * dvy - 3.0 * alpha * Ay;
+                        const double Jz = mr3 * dvz - 3.0 * alpha * Az;
+                        const double Sx = mr3 * dax - 6.0 * alpha * Jx - 3.0 * beta * Ax;
+                        const double Sy = mr3 * day - 6.0 * alpha * Jy - 3.0 * beta * Ay;
+                        const double Sz = mr3 * daz - 6.0 * alpha * Jz - 3.0 * beta * Az;
+                        D[0] += Ax; D[1] += Ay; D[2] += Az;
+                        D[3] += Jx; D[4] += Jy; D[5] += Jz;
+                        D[6] += Sx; D[7] += Sy; D[8] += Sz;
+                        D[ND - 3] += mr3 * djx - 9.0 * alpha * Sx - 9.0 * beta * Jx - 3.0 * gamma * Ax;
+                        D[ND - 2] += mr3 * djy - 9.0 * alpha * Sy - 9.0 * beta * Jy - 3.0 * gamma * Ay;
+                        D[ND - 1] += mr3 * djz - 9.0 * alpha * Sz - 9.0 * beta * Jz - 3.0 * gamma * Az;
+                    } else {
+                        const double a3 = -3.0 * alpha, a6 = a3 + a3, b3 = -3.0 * beta;
+                        const double jx = fma(a3, dxd, dvx), jy = fma(a3, dyd, dvy), jz = fma(a3, dzd, dvz);
+                        D[0] = fma(mr3, dxd, D[0]);
+                        D[1] = fma(mr3, dyd, D[1]);
+                        D[2] = fma(mr3, dzd, D[2]);
+                        D[3] = fma(mr3, jx, D[3]);
+                        D[4] = fma(mr3, jy, D[4]);
+                        D[5] = fma(mr3, jz, D[5]);
+                        D[6] = fma(mr3, fma(a6, jx, fma(b3, dxd, dax)), D[6]);
+                        D[7] = fma(mr3, fma(a6, jy, fma(b3, dyd, day)), D[7]);
+                        D[8] = fma(mr3, fma(a6, jz, fma(b3, dzd, daz)), D[8]);
+                    }
+                }
             }
-        }
+            if constexpr (MIXED || P32) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            if constexpr (MIXED)
-                ds_add(A[q], L[q], T[q]);
-            else
-                A[q] += T[q];
+                for (int q = 0; q < NF; ++q)
+                    ds_add(H[q], L[q], T[q]);
+            }
         }
     }
 
     // ---- combine the LPI lanes of each active particle (xor butterfly)
     double R[NV + 1];
+    if constexpr (P32) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-        R[q] = MIXED ? (double)A[q] + (double)L[q] : (double)A[q];
+        for (int q = 0; q < NF; ++q)
+            R[q] = (double)H[q] + (double)L[q];
+    } else if constexpr (MIXED) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            R[q] = D[q];
+#pragma unroll
+        for (int q = 0; q < NF; ++q)
+            R[3 + q] = (double)H[q] + (double)L[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            R[q] = D[q];
+    }
     R[NV] = phi;
 #pragma unroll
     for (int msk = 1; msk < LPI; msk <<= 1) {
@@ -283,16 +373,18 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     if (!valid || js != 0)
         return;
     // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
-    // potential: remove that term (computed the same way) when i was a source
+    // potential: remove that term, computed with the same operations
     if constexpr (!EPS0 && !POT) {
         if (i >= j0 && i < j1) {
-            const VT mi = J.m[i];
-            VT ri;
-            if constexpr (MIXED)
-                ri = __builtin_amdgcn_rsqf(fma((VT)0, (VT)0, fma((VT)0, (VT)0, fma((VT)0, (VT)0, e2))));
-            else
-                ri = rsqrt(e2);
-            R[NV] += (double)(mi * ri);
+            if constexpr (P32) {
+                const float e2f = (float)eps2;
+                const float ri = __builtin_amdgcn_rsqf(fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, e2f))));
+                R[NV] += (double)((float)J.m[i] * ri);
+            } else {
+                const double r2 = fma(0.0, 0.0, fma(0.0, 0.0, fma(0.0, 0.0, eps2)));
+                const double ri = MIXED ? rinv_mixed(r2) : rsqrt(r2);
+                R[NV] += J.m[i] * ri;
+            }
         }
     }
     if constexpr (INIT) {
@@ -359,7 +451,7 @@ using KF64 = void (*)(JRecF64, ForceWork, ForceOut, double *, int64_t, double);
 template <int PREC, bool EPS0, int NW>
 auto pick_lpi(int lpi_log2)
 {
-    using K = typename std::conditional<PREC == PREC_MIXED, KMixed, KF64>::type;
+    using K = typename std::conditional<PREC == PREC_MIXED || PREC == PREC_PAIR32, KMixed, KF64>::type;
     static const K tab[7] = {
         force_kernel<PREC, 1, NW, EPS0>,  force_kernel<PREC, 2, NW, EPS0>,
         force_kernel<PREC, 4, NW, EPS0>,  force_kernel<PREC, 8, NW, EPS0>,
@@ -441,9 +533,14 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     const dim3 block(64 * L.waves);
     const int prec = out.vec[0] ? c.cfg.precision : PREC_POT;
     const int rec = prof_begin(c, prec == PREC_POT ? PH_ENERGY : PH_FORCE, n_act_total);
-    if (prec == NBODY_PREC_MIXED) {
-        KMixed k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
-                        : pick_kernel<PREC_MIXED, false>(lg, L.waves);
+    if (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR) {
+        KMixed k;
+        if (prec == NBODY_PREC_MIXED)
+            k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
+                     : pick_kernel<PREC_MIXED, false>(lg, L.waves);
+        else
+            k = eps0 ? pick_kernel<PREC_PAIR32, true>(lg, L.waves)
+                     : pick_kernel<PREC_PAIR32, false>(lg, L.waves);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jm, w, out, part, n_act_total, eps2);
     } else {
         JRecF64 J = c.jd;

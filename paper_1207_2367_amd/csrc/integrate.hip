@@ -93,11 +93,11 @@ __global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF
         ap[d] = a + h * (j + h * (s * 0.5 + h * (c * (1.0 / 6))));
     }
     const double m = st.mass[i];
-    if (prec == NBODY_PREC_MIXED) {
+    if (prec != NBODY_PREC_FP64) {
         jm.x[i] = xp[0]; jm.y[i] = xp[1]; jm.z[i] = xp[2];
         jm.vx[i] = (float)vp[0]; jm.vy[i] = (float)vp[1]; jm.vz[i] = (float)vp[2];
         jm.ax[i] = (float)ap[0]; jm.ay[i] = (float)ap[1]; jm.az[i] = (float)ap[2];
-        jm.m[i] = (float)m;
+        jm.m[i] = m;
     } else {
         jd.x[i] = xp[0]; jd.y[i] = xp[1]; jd.z[i] = xp[2];
         jd.vx[i] = vp[0]; jd.vy[i] = vp[1]; jd.vz[i] = vp[2];

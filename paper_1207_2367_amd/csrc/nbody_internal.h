@@ -15,12 +15,12 @@ namespace nb {
 // ---------------------------------------------------------------- records
 // Source ("j") records: the predicted state of every particle at the block
 // time, structure-of-arrays so that a tile load is coalesced.
-//   mixed: x, y, z in FP64 (for the FP64 differences r_j - r_i), velocity,
-//          acceleration and mass in FP32          -> 52 bytes per particle
+//   mixed: x, y, z and mass in FP64 (they enter the FP64 acceleration and
+//          potential), velocity and acceleration in FP32 -> 56 bytes
 //   fp64 : every field FP64                       -> 80 bytes per particle
 struct JRecMixed {
-    double *x, *y, *z;
-    float *vx, *vy, *vz, *ax, *ay, *az, *m;
+    double *x, *y, *z, *m;
+    float *vx, *vy, *vz, *ax, *ay, *az;
 };
 struct JRecF64 {
     double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *m;

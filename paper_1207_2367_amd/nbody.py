@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libnbody.so")
 
 OK, EINVAL, EDEVICE, ENONFINITE, EDTMIN, ESTATE = 0, -1, -2, -3, -4, -5
-PREC_MIXED, PREC_FP64 = 0, 1
+PREC_MIXED, PREC_FP64, PREC_FP32PAIR = 0, 1, 2
 
 _lib = None
 

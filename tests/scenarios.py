@@ -61,7 +61,7 @@ def plummer1k():
     oracle, GPU FP64 and GPU mixed."""
     import ics
     import oracle
-    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    from paper_1207_2367_amd import PREC_FP32PAIR, PREC_FP64, PREC_MIXED, System
     m, x, v = ics.plummer(1024, 1001)
     it = oracle.Integrator(m, x, v, 1e-4)
     it.init(1.0)
@@ -76,7 +76,8 @@ def plummer1k():
         "dE_over_E": (sum(it.energy()[:2]) - e0) / e0,
         "dL_over_L": (np.linalg.norm(it.energy()[2]) - L0) / L0,
         "wall_s": t_or, "cores": len(os.sched_getaffinity(0))}}
-    for name, prec in (("gpu_fp64", PREC_FP64), ("gpu_mixed", PREC_MIXED)):
+    for name, prec in (("gpu_fp64", PREC_FP64), ("gpu_mixed", PREC_MIXED),
+                       ("gpu_fp32pair", PREC_FP32PAIR)):
         s = System(m, x, v, 1e-4, precision=prec)
         g0 = sum(s.energy()[:2])
         gL0 = np.linalg.norm(s.energy()[2])
@@ -98,14 +99,14 @@ def force64k():
     the oracle (all particles for N_act <= 8192, 1024 sampled otherwise)."""
     import ics
     import oracle
-    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    from paper_1207_2367_amd import PREC_FP32PAIR, PREC_FP64, PREC_MIXED, System
     n = 65536
     m, x, v = ics.plummer(n, 2002)
     a = ics.plummer_mean_acc(x)
     rng = np.random.default_rng(2003)
     res = {"config": "force64k", "n": n, "cases": []}
     systems = {}
-    for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
+    for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64), ("fp32pair", PREC_FP32PAIR)):
         s = System(m, x, v, 1e-4, precision=prec)
         s.set_state(x=x, v=v, a=a, t=np.zeros(n), dt=np.full(n, 1.0 / 16))
         systems[name] = s
