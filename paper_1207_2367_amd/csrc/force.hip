@@ -531,9 +531,11 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     double *part = w.split > 1 ? c.part : nullptr;
     const dim3 grid((unsigned)w.n_blocks, (unsigned)w.split);
     const dim3 block(64 * L.waves);
-    const int prec = out.vec[0] ? c.cfg.precision : PREC_POT;
-    const int rec = prof_begin(c, prec == PREC_POT ? PH_ENERGY : PH_FORCE, n_act_total);
-    if (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR) {
+    // no vector outputs: the energy pass (FP64 potential of the stored state)
+    const bool pot = out.vec[0] == nullptr;
+    const int prec = c.cfg.precision;
+    const int rec = prof_begin(c, pot ? PH_ENERGY : PH_FORCE, n_act_total);
+    if (!pot && (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR)) {
         KMixed k;
         if (prec == NBODY_PREC_MIXED)
             k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
@@ -545,7 +547,7 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     } else {
         JRecF64 J = c.jd;
         KF64 k;
-        if (prec == PREC_POT) {
+        if (pot) {
             // potential of the stored state: sources read straight from it
             J.x = c.st.pos;
             J.y = c.st.pos + c.n;
@@ -564,9 +566,9 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     if (e != hipSuccess || w.split <= 1)
         return e;
     const unsigned nb = (unsigned)((n_act_total + 255) / 256);
-    const int rr = prof_begin(c, prec == PREC_POT ? PH_ENERGY : PH_REDUCE);
+    const int rr = prof_begin(c, pot ? PH_ENERGY : PH_REDUCE);
     hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
-                       w.split, n_act_total, out, prec == PREC_POT ? 1 : 0);
+                       w.split, n_act_total, out, pot ? 1 : 0);
     prof_end(c, rr);
     return hipGetLastError();
 }

@@ -70,6 +70,15 @@ def gpu_system(m, x, v, a, eps, precision, **kw):
     return s
 
 
+def force(system, idx):
+    """nbody_force into NaN-filled outputs (so an output the kernel fails to
+    write cannot pass on stale memory)."""
+    na = len(idx)
+    out = [torch.full((na, 3), float("nan"), dtype=torch.float64, device="cuda") for _ in range(3)]
+    out.append(torch.full((na,), float("nan"), dtype=torch.float64, device="cuda"))
+    return system.force(idx, out=out)
+
+
 def log_case(**kw):
     print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
 

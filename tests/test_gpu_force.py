@@ -25,7 +25,7 @@ import torch
 
 import ics
 import oracle
-from gpu_helpers import cpu, gpu_system, kappa, log_case, plummer_inputs, rel_err_rows
+from gpu_helpers import cpu, force, gpu_system, kappa, log_case, plummer_inputs, rel_err_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,7 @@ def test_force_parity(inputs, prec, n_act):
     idx = ics.active_subset(n, n_act, 7 + n_act)
     ref = oracle.force(m, x, v, a, EPS, idx)
     s = gpu_system(m, x, v, a, EPS, prec)
-    got = s.force(idx)
+    got = force(s, idx)
     torch.cuda.synchronize()
     _check(prec, got, ref, kappa(m, x, v, a, EPS, idx))
 
@@ -91,7 +91,7 @@ def test_force_every_launch_shape(inputs, prec):
             for split in (1, 3, 16):
                 log_case(test="launch_shape", prec=prec, lpi=lpi, waves=waves, split=split)
                 s.set_launch(lpi, waves, split)
-                got = s.force(idx)
+                got = force(s, idx)
                 torch.cuda.synchronize()
                 _check(prec, got, ref, kap)
 
@@ -101,8 +101,8 @@ def test_force_deterministic(inputs, prec):
     m, x, v, a = inputs
     idx = ics.active_subset(m.shape[0], 1000, 3)
     s = gpu_system(m, x, v, a, EPS, prec)
-    r1 = [cpu(q).copy() for q in s.force(idx)]
-    r2 = [cpu(q).copy() for q in s.force(idx)]
+    r1 = [cpu(q).copy() for q in force(s, idx)]
+    r2 = [cpu(q).copy() for q in force(s, idx)]
     for p, q in zip(r1, r2):
         assert np.array_equal(p, q)
 
@@ -121,7 +121,7 @@ def test_force_unsoftened_kepler(prec):
     a = -w * w * x
     log_case(test="kepler_eps0", prec=prec)
     s = gpu_system(np.array([m1, m2]), x, v, a, 0.0, prec)
-    ga, gj, gs, gp = (cpu(q) for q in s.force([0, 1]))
+    ga, gj, gs, gp = (cpu(q) for q in force(s, [0, 1]))
     tol = {0: 1e-6, 1: 1e-13, 2: 1e-6}[prec]
     assert np.abs(ga + w ** 2 * x).max() < tol * w ** 2 * R
     assert np.abs(gj + w ** 2 * v).max() < tol * w ** 3 * R
@@ -149,7 +149,7 @@ def test_force_clusters(prec):
     s = gpu_system(m, x, v, a, EPS, prec, offsets=off)
     for shape in ((0, 0, 0), (1, 4, 1), (8, 1, 4), (64, 1, 2)):
         s.set_launch(*shape)
-        _check(prec, s.force(idx), ref, kap)
+        _check(prec, force(s, idx), ref, kap)
 
 
 def test_force_validate_rejects_bad_index():
@@ -173,7 +173,7 @@ def test_force_full_size_sampled(prec):
     log_case(test="full_size", prec=prec, n=n)
     s = gpu_system(m, x, v, a, EPS, prec)
     idx = np.arange(n)
-    got = [cpu(q) for q in s.force(idx)]
+    got = [cpu(q) for q in force(s, idx)]
     sample = ics.active_subset(n, 256, 99)
     ref = oracle.force(m, x, v, a, EPS, sample)
     _check(prec, [torch.as_tensor(g[sample]) for g in got], ref,
