@@ -8,6 +8,8 @@ benchmark).  Test infrastructure: not collected by pytest, run by hand:
     python tests/scenarios.py plummer1m      # 1M bodies to t = 0.125
     python tests/scenarios.py king256        # 256 King clusters to t = 1
     python tests/scenarios.py plummer8m      # 8M sources x 65,536 active
+    python tests/scenarios.py bfactor16k     # split-source on/off vs N_act
+    python tests/scenarios.py etascan        # energy error against eta
 """
 from __future__ import annotations
 
@@ -44,12 +46,24 @@ def _err_stats(e):
             "median": float(np.median(e)), "frac_le_1e-6": float((e <= 1e-6).mean())}
 
 
-def _run(system, t_end, profile=True):
+def _run(system, t_end, profile=True, pieces=1):
+    """Advance to t_end in `pieces` equal calls (each a multiple of dt_max
+    when t_end is), printing progress after each; returns summed stats."""
     if profile:
         system.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = system.step(t_end)
+    st = None
+    for k in range(1, pieces + 1):
+        s = system.step(t_end * k / pieces)
+        if st is None:
+            st = s
+        else:
+            for key in ("block_steps", "active_total", "interactions"):
+                st[key] += s[key]
+            st["hist"] = [a + b for a, b in zip(st["hist"], s["hist"])]
+        _log(f"  t = {t_end * k / pieces:.4f}: {st['block_steps']} block steps, "
+             f"{time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = system.profile(False) if profile else None
@@ -161,9 +175,18 @@ def plummer1m(t_end=0.125, n=1 << 20):
             res["force_check_t0"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
                                      zip(("acc", "jrk", "snp", "pot"), got, ref)}
         e0 = sum(s.energy()[:2])
-        st, wall, prof = _run(s, t_end)
+        st, wall, prof = _run(s, t_end, pieces=16)
+        na_log, pr_log, ms_log = s.force_log()
         e1 = sum(s.energy()[:2])
+        # share of the evaluation time by the paper's Fig. 7 groups of N_act
+        gt = {g: 0.0 for _, _, g in GROUPS}
+        for na_, ms_ in zip(na_log, ms_log):
+            for lo, hi, g in GROUPS:
+                if lo <= na_ <= hi:
+                    gt[g] += float(ms_)
+        tot = sum(gt.values()) or 1.0
         res[name] = {"dE_over_E": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                     "force_time_share_by_group": {g: gt[g] / tot for g in gt},
                      "interactions": st["interactions"], "wall_s": wall, "init_s": t_init,
                      "G_interactions_per_s": st["interactions"] / wall / 1e9,
                      "phase_ms": {k: v[0] for k, v in prof.items() if k != "pairs"},
@@ -193,7 +216,7 @@ def king256(t_end=1.0):
     # per-cluster energies through separate contexts would cost N_c^2 each;
     # the ensemble energy of the whole context is one call
     e0 = sum(s.energy()[:2])
-    st, wall, prof = _run(s, t_end)
+    st, wall, prof = _run(s, t_end, pieces=16)
     e1 = sum(s.energy()[:2])
     res["mixed"] = {"dE_over_E_total": (e1 - e0) / e0, "block_steps": st["block_steps"],
                     "interactions": st["interactions"], "wall_s": wall,
@@ -261,8 +284,75 @@ def plummer8m(n=1 << 23, n_act=65536):
     return res
 
 
+def bfactor16k(n=16384):
+    """Speed of the evaluation against active-set size for 16,384 sources
+    (the paper's Fig. 8 setting, 1M bodies over 64 GPUs): the split-source
+    factor and lanes per particle switched off (one lane per particle, one
+    split, 4 waves) against the autotuned shapes."""
+    import ics
+    from paper_1207_2367_amd import PREC_MIXED, System
+    m, x, v = ics.plummer(n, 2002)
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+    s.autotune(100.0)
+    rows = []
+    for b in range(0, 15):
+        na = 1 << b
+        idx = ics.active_subset(n, na, 100 + b)
+        r = {"n_act": na}
+        for name, shape in (("bfactor_off", (1, 4, 1)), ("autotuned", (0, 0, 0))):
+            s.set_launch(*shape)
+            r[name + "_launch"] = s.get_launch(na)
+            s.force(idx)
+            s.profile(True)
+            for _ in range(20):
+                s.force(idx)
+            prof = s.profile(False)
+            ms = prof["force"][0] / prof["force"][1] + (prof["reduce"][0] / 20 if prof["reduce"][1] else 0.0)
+            r[name + "_ms"] = ms
+            r[name + "_G_per_s"] = na * n / (ms * 1e-3) / 1e9
+        r["gain"] = r["bfactor_off_ms"] / r["autotuned_ms"]
+        rows.append(r)
+    return {"config": "bfactor16k", "n": n, "rows": rows}
+
+
+def etascan(ns=(1 << 15, 1 << 16), etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_end=10.0):
+    """Energy and angular-momentum error against eta (the paper's Fig. 1
+    experiment): Plummer spheres, 10 time units, the paper's average of the
+    relative errors at t = 1 .. 10, both the mixed and the FP64 paths."""
+    import ics
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, NBodyError, System
+    rows = []
+    for n in ns:
+        m, x, v = ics.plummer(n, 7000 + n % 997)
+        for eta in etas:
+            for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
+                s = System(m, x, v, 1e-4, precision=prec, eta=eta)
+                ek, ep, L = s.energy()
+                e0, l0 = ek + ep, np.linalg.norm(L)
+                de, dl, steps, inter, t0 = [], [], 0, 0.0, time.perf_counter()
+                try:
+                    for t in range(1, int(t_end) + 1):
+                        st = s.step(float(t))
+                        steps += st["block_steps"]
+                        inter += st["interactions"]
+                        ek, ep, L = s.energy()
+                        de.append(abs((ek + ep - e0) / e0))
+                        dl.append(abs((np.linalg.norm(L) - l0) / l0))
+                    err = None
+                except NBodyError as e:
+                    err = str(e)
+                rows.append({"n": n, "eta": eta, "precision": name,
+                             "dE_avg": float(np.mean(de)) if de else None,
+                             "dL_avg": float(np.mean(dl)) if dl else None,
+                             "block_steps": steps, "interactions": inter,
+                             "wall_s": time.perf_counter() - t0, "error": err})
+                _log(f"etascan {rows[-1]}")
+    return {"config": "etascan", "rows": rows}
+
+
 RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
-        "king256": king256, "plummer8m": plummer8m}
+        "king256": king256, "plummer8m": plummer8m, "bfactor16k": bfactor16k,
+        "etascan": etascan}
 
 
 def _default(o):
