@@ -45,10 +45,13 @@ PAPER_FLOPS_PER_PAIR = 97      # the paper's convention (Table 2)
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
 PEAK_FP32_DATASHEET = 157.3                          # counts packed FP32
 PEAK_FP64 = 78.6
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes over `bench.py --profile-pass` (profiles/), scaled by the
-# same counters on a 1 GiB copy; None until measured for this kernel build.
-TRAFFIC = None
+# HBM bytes per launch of the dominant kernel (mixed evaluation, N_act = N =
+# 65,536, LPI 1, 4 waves, split 16) from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes over `bench.py --profile-pass`, each scaled by what the counter
+# reads for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0): 29.71 MB read +
+# 83.89 MB written (profiles/force_mixed_plummer65536_counters.txt).  Must be
+# re-measured (or set to None) whenever that kernel changes.
+TRAFFIC = 113.6e6
 
 
 def parse():
@@ -198,6 +201,24 @@ def summarize_profile(d):
             short = key[0].replace("(anonymous namespace)::", "").split("(")[0][:90]
             out.append(f"{len(v):5d} {sum(v):9.3f} {statistics.mean(v):9.5f} {min(v):9.5f} "
                        f"{max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} ({key[3]})  {short}")
+        # the dominant kernel of the bench: the shape of the last mixed-mode
+        # evaluation longer than 1 ms (the full active set of the last timed
+        # step; later mixed launches are the small energy-error runs); its
+        # dispatches in launch order (autotune repetitions, warm-up, steps)
+        mixed = sorted((r for r in rows if "force_kernel<0," in r["Kernel_Name"]),
+                       key=lambda r: int(r["Start_Timestamp"]))
+        mixed_long = [r for r in mixed
+                      if int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) > 1_000_000]
+        if mixed_long:
+            r = mixed_long[-1]
+            shape = (r["Kernel_Name"], r["Grid_Size_X"], r["Grid_Size_Y"])
+            seq = [r for r in mixed if (r["Kernel_Name"], r["Grid_Size_X"], r["Grid_Size_Y"]) == shape]
+            seq.sort(key=lambda r: int(r["Start_Timestamp"]))
+            durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in seq]
+            kname = shape[0].replace("(anonymous namespace)::", "").split("(")[0]
+            out.append(f"# dominant kernel {kname} grid {shape[1]} x {shape[2]}: "
+                       f"{len(durs)} dispatches in launch order (ms): "
+                       + " ".join(f"{x:.4f}" for x in durs))
     for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         rows = list(csv.DictReader(open(f)))
         per = {}
@@ -209,10 +230,40 @@ def summarize_profile(d):
                    name.replace("(anonymous namespace)::", "").split("(")[0][:70], r["Grid_Size"])
             per.setdefault(key, {})
             per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        # listed: the dispatches of the dominant kernel's shape (the last
+        # mixed-mode evaluation longer than 1 ms) and the largest copy (the
+        # 1 GiB calibration copy of the profile pass)
+        dur = {}
+        for r in rows:
+            dur[int(r["Dispatch_Id"])] = (r["Kernel_Name"], int(r["Grid_Size"]),
+                                          int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        copies = [k_ for k_ in per if "copy" in k_[1].lower()]
+        mixed = [k_ for k_ in per if "force_kernel<0," in k_[1] and dur[k_[0]][2] > 1_000_000]
+        listed = []
+        if mixed:
+            dom = max(mixed, key=lambda k_: k_[0])
+            listed = [k_ for k_ in mixed if k_[1:] == dom[1:]]
+        if copies:
+            listed.append(max(copies, key=lambda k_: int(k_[2])))
         out.append(f"# {os.path.basename(f)}")
-        for key in sorted(per):
+        for key in sorted(listed):
             vals = " ".join(f"{k}={v:.6g}" for k, v in sorted(per[key].items()))
-            out.append(f"dispatch {key[0]:5d} grid {key[2]:>9}  {key[1]}  {vals}")
+            out.append(f"dispatch {key[0]:5d} grid {key[2]:>9} {dur[key[0]][2] / 1e6:8.3f} ms  "
+                       f"{key[1]}  {vals}")
+        # calibration: the 1 GiB copy against the bytes it moves; then the
+        # dominant kernel (the last mixed-mode evaluation longer than 1 ms)
+        # scaled by it
+        if copies and mixed:
+            cp = max(copies, key=lambda k_: int(k_[2]))
+            dom = max(mixed, key=lambda k_: k_[0])
+            for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+                if cname in per[cp] and cname in per[dom]:
+                    fac = (1 << 30) / (per[cp][cname] * 1024.0)
+                    byt = per[dom][cname] * 1024.0 * fac
+                    out.append(f"# {cname}: 1 GiB copy (dispatch {cp[0]}) counts {per[cp][cname]:.6g} KiB "
+                               f"-> factor {fac:.4f}; dominant kernel dispatch {dom[0]} ({dom[1]}, grid "
+                               f"{dom[2]}, {dur[dom[0]][2] / 1e6:.3f} ms) {per[dom][cname]:.6g} KiB "
+                               f"-> {byt / 1e6:.2f} MB per launch")
     print("\n".join(out))
 
 
@@ -318,6 +369,7 @@ def main():
             "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED, 2),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4),
             "traffic": TRAFFIC,
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "evaluation (force) kernel, N_act = N",
             "kernel_avg_ms": round(avg_ms, 5), "flops_per_pair": FLOPS_PER_PAIR,
             "peak_basis": "FP32 vector without packed math: 256 CU x 64 lanes x 2 flop x 2.4 GHz "

@@ -24,6 +24,8 @@
 //     ~720/h^5 but the jerk's and snap's by at most ~1/h^4 and ~1/h^3;
 //   - the LPI lanes of a particle are combined by a xor butterfly of wave
 //     shuffles (bitwise identical on every lane, fixed order);
+//   - the FP64 passes take 1/r from the same FP32 seed, refined to FP64
+//     accuracy by one third-order step;
 //   - the energy variant (PREC_POT) sums m_j / r over j > i only, FP64;
 //   - grid.y = B splits the sources; partial results go to a [B][10][n_act]
 //     buffer that a second kernel sums in fixed order b = 0 .. B-1, so the
@@ -84,6 +86,43 @@ __device__ __forceinline__ double rinv_mixed(double r2)
     const double y0 = (double)__builtin_amdgcn_rsqf((float)r2);
     const double res = fma(-r2 * y0, y0, 1.0);   // 1 - r2 y0^2
     return fma(0.5 * y0, res, y0);
+}
+
+// 1/sqrt(r2) to FP64 accuracy for the FP64 passes: the same FP32 seed y0
+// (relative error |d| below ~2e-7 with the rounding of r2 to FP32), then the
+// third-order step y0 (1 + e/2 + 3e^2/8), e = 1 - r2 y0^2 = O(2d), whose
+// truncation error (5/16) e^3 is far below an FP64 ulp; the result is within
+// about one ulp.  Valid while r2 is a normal FP32 number (r from ~1e-19 to
+// ~1e19), which the softened distances of every supported system are.
+__device__ __forceinline__ double rinv_f64(double r2)
+{
+    const double y0 = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double e = fma(-r2 * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
+// Potential terms of one LDS tile for one lane: phi -= m_j / r_ij over the
+// lane's PER sources, FP64.  MASK keeps only sources with tile slot t > lim
+// (the diagonal tiles of the energy pass, where j > i must be tested).
+template <int PER, int LPI, bool MASK, bool EPS0>
+__device__ __forceinline__ double pot_tile(const double *sx, const double *sy,
+                                           const double *sz, const double *sm,
+                                           double xi, double yi, double zi, double eps2,
+                                           int js, int lim, double phi)
+{
+#pragma unroll 8
+    for (int p = 0; p < PER; ++p) {
+        const int t = js + p * LPI;
+        const double dx = sx[t] - xi, dy = sy[t] - yi, dz = sz[t] - zi;
+        const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+        double rinv = rinv_f64(r2);
+        if constexpr (EPS0)
+            rinv = r2 > 0.0 ? rinv : 0.0;
+        if constexpr (MASK)
+            rinv = t > lim ? rinv : 0.0;
+        phi = fma(-sm[t], rinv, phi);
+    }
+    return phi;
 }
 
 template <int PREC, int LPI, int NW, bool EPS0>
@@ -205,6 +244,21 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         }
         __syncthreads();
 
+        if constexpr (POT) {
+            // slots t > i - t0 hold j > i; only tiles reaching down to the
+            // workgroup's particles need the test (uniform branch)
+            if (t0 <= i_hi) {
+                const int64_t d = i - t0;
+                const int lim = d < -1 ? -1 : (d > NT ? NT : (int)d);
+                phi = pot_tile<PER, LPI, true, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2,
+                                                     js, lim, phi);
+            } else {
+                phi = pot_tile<PER, LPI, false, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2,
+                                                      js, 0, phi);
+            }
+            continue;
+        }
+
         // a short FP32 partial keeps its rounding small (64 pairs measured
         // 3x better than 256 for the jerk, at ~1% more instructions)
         constexpr int FOLD = (MIXED || P32) ? (PER < 64 ? PER : 64) : PER;
@@ -254,17 +308,11 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 if constexpr (MIXED)
                     rinv = rinv_mixed(r2);
                 else
-                    rinv = rsqrt(r2);
+                    rinv = rinv_f64(r2);
                 if constexpr (EPS0)
                     rinv = r2 > 0.0 ? rinv : 0.0;
-                if constexpr (POT) {
-                    if (t0 <= i_hi)   // a tile that may hold j <= i (uniform test)
-                        rinv = t0 + t > i ? rinv : 0.0;
-                }
                 const double mrinv = s_m[t] * rinv;
                 phi -= mrinv;
-                if constexpr (POT)
-                    continue;
                 const double rinv2 = rinv * rinv;
                 const double mr3 = mrinv * rinv2;
                 if constexpr (MIXED) {
@@ -382,7 +430,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 R[NV] += (double)((float)J.m[i] * ri);
             } else {
                 const double r2 = fma(0.0, 0.0, fma(0.0, 0.0, fma(0.0, 0.0, eps2)));
-                const double ri = MIXED ? rinv_mixed(r2) : rsqrt(r2);
+                const double ri = MIXED ? rinv_mixed(r2) : rinv_f64(r2);
                 R[NV] += J.m[i] * ri;
             }
         }
@@ -415,33 +463,43 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
 }
 
 // Sum the B split-source partials of every active slot in the fixed order
-// b = 0 .. B-1 (Table 1, section 4 of the paper).
+// b = 0 .. B-1 (Table 1, section 4 of the paper).  One thread per (quantity,
+// active slot), so reads are coalesced over slots; the loads of 16 splits
+// are issued before their adds (the order of the adds is unchanged), which
+// keeps a tiny active set with a large B from waiting out B serial
+// round trips to L2.
 __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t B,
                                                     int64_t n_act, ForceOut out,
                                                     int pot_only)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= n_act)
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int nq = pot_only ? 1 : 10;
+    if (t >= n_act * nq)
         return;
-    double R[10];
+    const int q = pot_only ? 9 : (int)(t / n_act);
+    const int64_t k = pot_only ? t : t - (int64_t)q * n_act;
+    const double *p = part + (int64_t)q * n_act + k;
+    const int64_t stride = 10 * n_act;
+    constexpr int U = 16;
+    double r = 0.0;
+    int b = 0;
+    for (; b + U <= B; b += U) {
+        double v[U];
 #pragma unroll
-    for (int q = 0; q < 10; ++q)
-        R[q] = 0.0;
-    for (int b = 0; b < B; ++b) {
-        const double *pb = part + (int64_t)b * 10 * n_act + k;
+        for (int u = 0; u < U; ++u)
+            v[u] = p[(int64_t)(b + u) * stride];
 #pragma unroll
-        for (int q = 0; q < 10; ++q)
-            R[q] += pb[(int64_t)q * n_act];
+        for (int u = 0; u < U; ++u)
+            r += v[u];
     }
-    if (!pot_only) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
+    for (; b < B; ++b)
+        r += p[(int64_t)b * stride];
+    if (q == 9) {
+        if (out.pot)
+            out.pot[k] = r;
+    } else {
+        out.vec[q / 3][k * out.sk + (q % 3) * out.sd] = r;
     }
-    if (out.pot)
-        out.pot[k] = R[9];
 }
 
 // ---- dispatch table over the template parameters
@@ -565,7 +623,7 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || w.split <= 1)
         return e;
-    const unsigned nb = (unsigned)((n_act_total + 255) / 256);
+    const unsigned nb = (unsigned)((n_act_total * (pot ? 1 : 10) + 255) / 256);
     const int rr = prof_begin(c, pot ? PH_ENERGY : PH_REDUCE);
     hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
                        w.split, n_act_total, out, pot ? 1 : 0);

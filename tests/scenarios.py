@@ -153,7 +153,8 @@ def _hist_groups(hist):
 def plummer1m(t_end=0.125, n=1 << 20):
     """1M-body Plummer sphere (seed 3003), eps 1e-4, eta 0.45, to t = 0.125:
     mixed and FP64 paths, energy error, block N_act histogram, throughput,
-    per-phase time; sampled forces checked against the oracle at t = 0."""
+    per-phase time; sampled forces checked against the oracle at t = 0 and
+    at t = 0.125."""
     import ics
     import oracle
     from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
@@ -178,6 +179,14 @@ def plummer1m(t_end=0.125, n=1 << 20):
         st, wall, prof = _run(s, t_end, pieces=16)
         na_log, pr_log, ms_log = s.force_log()
         e1 = sum(s.energy()[:2])
+        if name == "mixed":
+            # the same sampled check at t_end (synchronized state = sources)
+            st_end = s.get_state()
+            xe, ve, ae = (st_end[q].cpu().numpy() for q in ("x", "v", "a"))
+            got = [q.cpu().numpy() for q in s.force(smp)]
+            ref = oracle.force(m, xe, ve, ae, 1e-4, smp)
+            res["force_check_t_end"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
+                                        zip(("acc", "jrk", "snp", "pot"), got, ref)}
         # share of the evaluation time by the paper's Fig. 7 groups of N_act
         gt = {g: 0.0 for _, _, g in GROUPS}
         for na_, ms_ in zip(na_log, ms_log):

@@ -25,35 +25,19 @@ import torch
 
 import ics
 import oracle
-from gpu_helpers import cpu, force, gpu_system, kappa, log_case, plummer_inputs, rel_err_rows
+from gpu_helpers import (FORCE_TOL, check_force, cpu, force, gpu_system, kappa, log_case,
+                         plummer_inputs)
 
 pytestmark = pytest.mark.gpu
 
-# precision -> tolerance factors for (a, da, d2a, potential)
-TOL = {0: (1e-11, 1e-6, 2e-6, 1e-11), 1: (1e-12, 1e-12, 1e-11, 1e-12),
-       2: (1e-6, 1e-6, 2e-6, 1e-6)}
+TOL = FORCE_TOL
 PRECS = [0, 1, 2]
 IDS = ["mixed", "fp64", "fp32pair"]
 EPS = 1e-4
 
 
 def _check(prec, got, ref, kap):
-    tol = TOL[prec]
-    ga, gj, gs, gp = (cpu(q) for q in got)
-    ra, rj, rs, rp = ref
-    errs = [rel_err_rows(ga, ra), rel_err_rows(gj, rj), rel_err_rows(gs, rs),
-            rel_err_rows(gp, rp)]
-    worst = [float(e.max()) for e in errs]
-    print("max rel err a %.2e da %.2e d2a %.2e pot %.2e" % tuple(worst), flush=True)
-    print("p99 %s | within 1e-6: %s | max kappa %s" % (
-        [f"{np.percentile(e, 99):.1e}" for e in errs],
-        [f"{(e <= 1e-6).mean():.4f}" for e in errs],
-        [f"{k:.1f}" for k in kap.max(0)]), flush=True)
-    for q, e in enumerate(errs):
-        bound = tol[q] * kap[:, q]
-        bad = np.nonzero(e > bound)[0]
-        assert bad.size == 0, (q, bad[:5], e[bad[:5]], kap[bad[:5], q])
-    return worst
+    return check_force(TOL[prec], got, ref, kap)
 
 
 @pytest.fixture(scope="module")
@@ -166,19 +150,26 @@ def test_force_validate_rejects_bad_index():
 @pytest.mark.parametrize("prec", PRECS, ids=IDS)
 def test_force_full_size_sampled(prec):
     """The N = 65,536 Plummer sphere with every particle active, in the
-    launch shape the benchmark uses: 256 sampled particles against the
-    oracle, one by one."""
+    launch shapes the benchmark times (the autotuner's choice after the same
+    150 ms search, and (1, 4, 16), its usual result) and the heuristic one:
+    256 sampled particles against the oracle, one by one, and the third law
+    over the whole system."""
     n = 65536
     m, x, v, a = plummer_inputs(n, 2002)
-    log_case(test="full_size", prec=prec, n=n)
     s = gpu_system(m, x, v, a, EPS, prec)
     idx = np.arange(n)
-    got = [cpu(q) for q in force(s, idx)]
     sample = ics.active_subset(n, 256, 99)
     ref = oracle.force(m, x, v, a, EPS, sample)
-    _check(prec, [torch.as_tensor(g[sample]) for g in got], ref,
-           kappa(m, x, v, a, EPS, sample))
-    # third law over the whole system
+    kap = kappa(m, x, v, a, EPS, sample)
     mm = m[:, None]
-    scale = np.abs(mm * got[0]).sum()
-    assert np.abs((mm * got[0]).sum(0)).max() < (1e-6 if prec == 2 else 1e-13) * scale
+    for shape in ((0, 0, 0), (1, 4, 16), "tuned"):
+        if shape == "tuned":
+            s.set_launch(0, 0, 0)
+            s.autotune(150.0)
+        else:
+            s.set_launch(*shape)
+        log_case(test="full_size", prec=prec, n=n, launch=s.get_launch(n))
+        got = [cpu(q) for q in force(s, idx)]
+        _check(prec, [torch.as_tensor(g[sample]) for g in got], ref, kap)
+        scale = np.abs(mm * got[0]).sum()
+        assert np.abs((mm * got[0]).sum(0)).max() < (1e-6 if prec == 2 else 1e-13) * scale
