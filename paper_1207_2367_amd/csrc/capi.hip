@@ -708,19 +708,7 @@ int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3])
     if (!ctx)
         return NBODY_EINVAL;
     Ctx &c = ctx->c;
-    HIPCHK(c, launch_segments(c, nullptr, c.n, c.stream));
-    ForceOut out{};
-    out.pot = c.d_phi;
-    out.sk = 1;
-    out.sd = c.n;
-    // potential-only FP64 pass (vec[0] == nullptr selects it)
-    const int64_t typ = c.nc == 1 ? c.n : std::max<int64_t>(1, c.n / c.nc);
-    Launch L0 = c.pinned;
-    c.pinned = Launch{};
-    int rc = run_force(c, nullptr, c.n, typ, out);
-    c.pinned = L0;
-    if (rc)
-        return rc;
+    HIPCHK(c, launch_energy_pot(c, c.d_phi, c.stream));
     const int rec = prof_begin(c, PH_ENERGY);
     HIPCHK(c, launch_energy_sums(c, c.d_phi, c.d_red + c.red_cap - 8, c.stream));
     prof_end(c, rec);

@@ -26,7 +26,8 @@
 //     shuffles (bitwise identical on every lane, fixed order);
 //   - the FP64 passes take 1/r from the same FP32 seed, refined to FP64
 //     accuracy by one third-order step;
-//   - the energy variant (PREC_POT) sums m_j / r over j > i only, FP64;
+//   - the potential energy (energy_kernel) takes every pair once, with a
+//     cyclic half-window per particle that gives every workgroup equal work;
 //   - grid.y = B splits the sources; partial results go to a [B][10][n_act]
 //     buffer that a second kernel sums in fixed order b = 0 .. B-1, so the
 //     result does not depend on scheduling (no float atomics anywhere).
@@ -36,9 +37,9 @@ namespace nb {
 
 namespace {
 
-// kernel variants: the two public mixed modes, the FP64 path, the energy
-// pass and the start-up pass
-constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_POT = 2, PREC_INIT = 3, PREC_PAIR32 = 4;
+// kernel variants: the two public mixed modes, the FP64 path and the
+// start-up pass
+constexpr int PREC_MIXED = 0, PREC_F64 = 1, PREC_INIT = 3, PREC_PAIR32 = 4;
 
 // Knuth's two-sum: (hi, lo) += p without rounding loss in the (hi, lo) pair.
 __device__ __forceinline__ void ds_add(float &hi, float &lo, float p)
@@ -66,10 +67,6 @@ struct Smem<PREC_PAIR32> {
 };
 template <>
 struct Smem<PREC_F64> {
-    using R = JRecF64;
-};
-template <>
-struct Smem<PREC_POT> {
     using R = JRecF64;
 };
 template <>
@@ -101,25 +98,23 @@ __device__ __forceinline__ double rinv_f64(double r2)
     return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
-// Potential terms of one LDS tile for one lane: phi -= m_j / r_ij over the
-// lane's PER sources, FP64.  MASK keeps only sources with tile slot t > lim
-// (the diagonal tiles of the energy pass, where j > i must be tested).
-template <int PER, int LPI, bool MASK, bool EPS0>
+// Potential terms of one LDS tile of NT sources for one lane: phi -= m_j /
+// r_ij, FP64.  MASK keeps only the tile slots lo <= t <= hi.
+template <int NT, bool MASK, bool EPS0>
 __device__ __forceinline__ double pot_tile(const double *sx, const double *sy,
                                            const double *sz, const double *sm,
                                            double xi, double yi, double zi, double eps2,
-                                           int js, int lim, double phi)
+                                           int lo, int hi, double phi)
 {
 #pragma unroll 8
-    for (int p = 0; p < PER; ++p) {
-        const int t = js + p * LPI;
+    for (int t = 0; t < NT; ++t) {
         const double dx = sx[t] - xi, dy = sy[t] - yi, dz = sz[t] - zi;
         const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
         double rinv = rinv_f64(r2);
         if constexpr (EPS0)
             rinv = r2 > 0.0 ? rinv : 0.0;
         if constexpr (MASK)
-            rinv = t > lim ? rinv : 0.0;
+            rinv = (t >= lo && t <= hi) ? rinv : 0.0;
         phi = fma(-sm[t], rinv, phi);
     }
     return phi;
@@ -136,7 +131,6 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     constexpr int PER = NT / LPI;    // pairs per lane per tile
     constexpr bool MIXED = PREC == PREC_MIXED;
     constexpr bool P32 = PREC == PREC_PAIR32;
-    constexpr bool POT = PREC == PREC_POT;
     constexpr bool INIT = PREC == PREC_INIT;
     constexpr int NV = INIT ? 12 : 9;   // vector outputs (3 components each)
     // FP32 accumulators (mixed: jerk and snap; FP32-pair mode: all nine);
@@ -146,8 +140,8 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     using VT = typename std::conditional<MIXED || P32, float, double>::type;
 
     __shared__ double s_x[NT], s_y[NT], s_z[NT], s_m[NT];
-    __shared__ VT s_vx[POT ? 1 : NT], s_vy[POT ? 1 : NT], s_vz[POT ? 1 : NT];
-    __shared__ VT s_ax[POT ? 1 : NT], s_ay[POT ? 1 : NT], s_az[POT ? 1 : NT];
+    __shared__ VT s_vx[NT], s_vy[NT], s_vz[NT];
+    __shared__ VT s_ax[NT], s_ay[NT], s_az[NT];
     __shared__ double s_jx[INIT ? NT : 1], s_jy[INIT ? NT : 1], s_jz[INIT ? NT : 1];
 
     // ---- which active slots and which sources this workgroup takes
@@ -179,11 +173,8 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     const int64_t i = w.idx ? (int64_t)w.idx[kk] : kk;
 
     const double xi = J.x[i], yi = J.y[i], zi = J.z[i];
-    VT vxi = 0, vyi = 0, vzi = 0, axi = 0, ayi = 0, azi = 0;
-    if constexpr (!POT) {
-        vxi = J.vx[i]; vyi = J.vy[i]; vzi = J.vz[i];
-        axi = J.ax[i]; ayi = J.ay[i]; azi = J.az[i];
-    }
+    const VT vxi = J.vx[i], vyi = J.vy[i], vzi = J.vz[i];
+    const VT axi = J.ax[i], ayi = J.ay[i], azi = J.az[i];
     double jxi = 0, jyi = 0, jzi = 0;
     if constexpr (INIT) {
         jxi = J.jx[i]; jyi = J.jy[i]; jzi = J.jz[i];
@@ -204,17 +195,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     }
     double phi = 0.0;
 
-    // energy pass: only pairs j > i (the index list is the identity there),
-    // so tiles entirely at or below the workgroup's first particle are skipped
-    int64_t t_first = j0;
-    int64_t i_hi = 0;
-    if constexpr (POT) {
-        const int64_t i_lo = kb;
-        i_hi = (kb + IB < s1 ? kb + IB : s1) - 1;
-        if (i_lo + 1 > j0)
-            t_first = j0 + (i_lo + 1 - j0) / NT * NT;
-    }
-    for (int64_t t0 = t_first; t0 < j1; t0 += NT) {
+    for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
         const int64_t jj = t0 + tid;
         if (jj < j1) {
@@ -222,10 +203,8 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
             s_y[tid] = J.y[jj];
             s_z[tid] = J.z[jj];
             s_m[tid] = J.m[jj];
-            if constexpr (!POT) {
-                s_vx[tid] = J.vx[jj]; s_vy[tid] = J.vy[jj]; s_vz[tid] = J.vz[jj];
-                s_ax[tid] = J.ax[jj]; s_ay[tid] = J.ay[jj]; s_az[tid] = J.az[jj];
-            }
+            s_vx[tid] = J.vx[jj]; s_vy[tid] = J.vy[jj]; s_vz[tid] = J.vz[jj];
+            s_ax[tid] = J.ax[jj]; s_ay[tid] = J.ay[jj]; s_az[tid] = J.az[jj];
             if constexpr (INIT) {
                 s_jx[tid] = J.jx[jj]; s_jy[tid] = J.jy[jj]; s_jz[tid] = J.jz[jj];
             }
@@ -234,30 +213,13 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
             s_y[tid] = NULL_POS;
             s_z[tid] = NULL_POS;
             s_m[tid] = 0.0;
-            if constexpr (!POT) {
-                s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
-                s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
-            }
+            s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
+            s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
             if constexpr (INIT) {
                 s_jx[tid] = 0; s_jy[tid] = 0; s_jz[tid] = 0;
             }
         }
         __syncthreads();
-
-        if constexpr (POT) {
-            // slots t > i - t0 hold j > i; only tiles reaching down to the
-            // workgroup's particles need the test (uniform branch)
-            if (t0 <= i_hi) {
-                const int64_t d = i - t0;
-                const int lim = d < -1 ? -1 : (d > NT ? NT : (int)d);
-                phi = pot_tile<PER, LPI, true, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2,
-                                                     js, lim, phi);
-            } else {
-                phi = pot_tile<PER, LPI, false, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2,
-                                                      js, 0, phi);
-            }
-            continue;
-        }
 
         // a short FP32 partial keeps its rounding small (64 pairs measured
         // 3x better than 256 for the jerk, at ~1% more instructions)
@@ -422,7 +384,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         return;
     // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
     // potential: remove that term, computed with the same operations
-    if constexpr (!EPS0 && !POT) {
+    if constexpr (!EPS0) {
         if (i >= j0 && i < j1) {
             if constexpr (P32) {
                 const float e2f = (float)eps2;
@@ -450,16 +412,97 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         for (int q = 0; q < 10; ++q)
             pb[(int64_t)q * n_act_total] = R[q];
     } else {
-        if constexpr (!POT) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
-        }
+            for (int d = 0; d < 3; ++d)
+                out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
         if (out.pot)
             out.pot[k] = R[NV];
     }
+}
+
+// Potential energy of the stored state (paper Sect. 5.1): every unordered
+// pair of a cluster once, FP64.  Particle i (local index l in a cluster of
+// size n_c) takes the sources l + 1 .. l + W_l taken cyclically, with
+// W_l = (n_c - 1) / 2 for odd n_c and, for even n_c, n_c / 2 for l < n_c / 2
+// and n_c / 2 - 1 otherwise: each pair at cyclic distance d < n_c / 2 is
+// then taken by exactly one of its ends, and the pair at d = n_c / 2 by the
+// end with the smaller index, so sum_l W_l = n_c (n_c - 1) / 2 and every
+// workgroup does the same work (no triangle).  A workgroup holds IB = 256
+// consecutive particles, one per lane; the union of their windows (virtual
+// positions ib0 + 1 .. last + W, folded back into the cluster) goes through
+// LDS in tiles of 256, split over grid.y = B; lanes mask only the tiles at
+// the two ends of the union.  Output: partial sums -sum m_j / r_ij per
+// particle and split, out[b * bstride + i].
+template <bool EPS0>
+__global__ __launch_bounds__(256) void energy_kernel(const double *X, const double *Y,
+                                                     const double *Z, const double *M,
+                                                     ForceWork w, double *out, int64_t bstride,
+                                                     double eps2)
+{
+    constexpr int NT = 256;
+    __shared__ double s_x[NT], s_y[NT], s_z[NT], s_m[NT];
+    const int64_t g = blockIdx.x;
+    const int b = blockIdx.y;
+    int c = 0;
+    int64_t gfirst = 0;
+    if (w.blk_cluster) {
+        c = w.blk_cluster[g];
+        if (c < 0)
+            return;  // grid padding past the last i-block
+        gfirst = w.blk_first[c];
+    }
+    const int64_t o0 = w.off[c];
+    const int64_t nc = w.off[c + 1] - o0;
+    const int64_t ib0 = (g - gfirst) * NT;          // local index of lane 0's particle
+    const int64_t last = (ib0 + NT < nc ? ib0 + NT : nc) - 1;
+    const int tid = threadIdx.x;
+    const int64_t l = ib0 + tid;
+    const bool valid = l < nc;
+    const int64_t half = nc / 2;
+    const int64_t wl = (nc & 1) ? half : (l < half ? half : half - 1);
+    const int64_t wmin = (nc & 1) ? half : half - 1;   // smallest window of the cluster
+    const int64_t i = o0 + (valid ? l : ib0);
+    const double xi = X[i], yi = Y[i], zi = Z[i];
+
+    // this split's share of the union of the windows, in whole tiles
+    const int64_t u_beg = ib0 + 1, u_end = last + half + 1;
+    int64_t chunk = (u_end - u_beg + w.split - 1) / w.split;
+    chunk = (chunk + NT - 1) / NT * NT;
+    const int64_t u0 = u_beg + (int64_t)b * chunk;
+    const int64_t u1 = u0 + chunk < u_end ? u0 + chunk : u_end;
+
+    double phi = 0.0;
+    for (int64_t t0 = u0; t0 < u1; t0 += NT) {
+        __syncthreads();
+        const int64_t u = t0 + tid;
+        if (u < u1) {
+            const int64_t j = o0 + (u < nc ? u : u - nc);   // u < 2 n_c always
+            s_x[tid] = X[j];
+            s_y[tid] = Y[j];
+            s_z[tid] = Z[j];
+            s_m[tid] = M[j];
+        } else {
+            s_x[tid] = NULL_POS;
+            s_y[tid] = NULL_POS;
+            s_z[tid] = NULL_POS;
+            s_m[tid] = 0.0;
+        }
+        __syncthreads();
+        // slots s of this tile with 1 <= t0 + s - l <= w_l; every lane's
+        // range covers the whole tile when t0 > last and t0 + NT - 1 <= ib0 + wmin
+        if (t0 > last && t0 + NT - 1 <= ib0 + wmin) {
+            phi = pot_tile<NT, false, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2, 0, NT - 1, phi);
+        } else {
+            const int64_t lo = l + 1 - t0, hi = l + wl - t0;
+            const int slo = lo < 0 ? 0 : (lo > NT ? NT : (int)lo);
+            const int shi = hi < -1 ? -1 : (hi > NT - 1 ? NT - 1 : (int)hi);
+            phi = pot_tile<NT, true, EPS0>(s_x, s_y, s_z, s_m, xi, yi, zi, eps2, slo, shi, phi);
+        }
+    }
+    if (valid)
+        out[(int64_t)b * bstride + i] = phi;
 }
 
 // Sum the B split-source partials of every active slot in the fixed order
@@ -589,11 +632,9 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     double *part = w.split > 1 ? c.part : nullptr;
     const dim3 grid((unsigned)w.n_blocks, (unsigned)w.split);
     const dim3 block(64 * L.waves);
-    // no vector outputs: the energy pass (FP64 potential of the stored state)
-    const bool pot = out.vec[0] == nullptr;
     const int prec = c.cfg.precision;
-    const int rec = prof_begin(c, pot ? PH_ENERGY : PH_FORCE, n_act_total);
-    if (!pot && (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR)) {
+    const int rec = prof_begin(c, PH_FORCE, n_act_total);
+    if (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR) {
         KMixed k;
         if (prec == NBODY_PREC_MIXED)
             k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
@@ -603,31 +644,71 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
                      : pick_kernel<PREC_PAIR32, false>(lg, L.waves);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jm, w, out, part, n_act_total, eps2);
     } else {
-        JRecF64 J = c.jd;
-        KF64 k;
-        if (pot) {
-            // potential of the stored state: sources read straight from it
-            J.x = c.st.pos;
-            J.y = c.st.pos + c.n;
-            J.z = c.st.pos + 2 * c.n;
-            J.m = c.st.mass;
-            k = eps0 ? pick_kernel<PREC_POT, true>(lg, L.waves)
-                     : pick_kernel<PREC_POT, false>(lg, L.waves);
-        } else {
-            k = eps0 ? pick_kernel<PREC_F64, true>(lg, L.waves)
-                     : pick_kernel<PREC_F64, false>(lg, L.waves);
-        }
-        hipLaunchKernelGGL(k, grid, block, 0, s, J, w, out, part, n_act_total, eps2);
+        KF64 k = eps0 ? pick_kernel<PREC_F64, true>(lg, L.waves)
+                      : pick_kernel<PREC_F64, false>(lg, L.waves);
+        hipLaunchKernelGGL(k, grid, block, 0, s, c.jd, w, out, part, n_act_total, eps2);
     }
     prof_end(c, rec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || w.split <= 1)
         return e;
-    const unsigned nb = (unsigned)((n_act_total * (pot ? 1 : 10) + 255) / 256);
-    const int rr = prof_begin(c, pot ? PH_ENERGY : PH_REDUCE);
+    const unsigned nb = (unsigned)((n_act_total * 10 + 255) / 256);
+    const int rr = prof_begin(c, PH_REDUCE);
     hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
-                       w.split, n_act_total, out, pot ? 1 : 0);
+                       w.split, n_act_total, out, 0);
     prof_end(c, rr);
+    return hipGetLastError();
+}
+
+// Potential of the stored state for the energy: phi[i] = -sum over the
+// particle's half-window of m_j / r_ij (every pair of a cluster once).
+hipError_t launch_energy_pot(Ctx &c, double *phi, hipStream_t s)
+{
+    constexpr int64_t IB = 256;
+    const int64_t n = c.n;
+    hipError_t e = launch_segments(c, nullptr, n, s);
+    if (e != hipSuccess)
+        return e;
+    ForceWork w{};
+    w.seg = c.d_seg;
+    w.off = c.d_off;
+    w.nc = c.nc;
+    if (c.nc == 1) {
+        w.n_blocks = (n + IB - 1) / IB;
+    } else {
+        const int64_t cap = n / IB + c.nc + 1;
+        if ((e = launch_blocks(c, IB, cap, s)) != hipSuccess)
+            return e;
+        w.blk_cluster = c.d_blk_cluster;
+        w.blk_first = c.d_blk_first;
+        w.n_blocks = cap;
+    }
+    // splits: up to ~2048 workgroups, at least two tiles per split, and the
+    // partial sums within the split buffer
+    int64_t ncmax = 0;
+    for (size_t k = 0; k + 1 < c.off.size(); ++k)
+        ncmax = std::max(ncmax, c.off[k + 1] - c.off[k]);
+    int split = 1;
+    while (w.n_blocks * split * 2 <= 2048 && (ncmax / 2 + IB) / (split * 2) >= 2 * IB &&
+           (int64_t)split * 2 * n <= c.part_cap)
+        split <<= 1;
+    w.split = split;
+    const double *X = c.st.pos, *Y = c.st.pos + n, *Z = c.st.pos + 2 * n;
+    double *dst = split > 1 ? c.part + 9 * n : phi;
+    const int64_t bstride = 10 * n;   // the [B][10][n] layout of the split buffer, slot 9
+    auto k = c.eps == 0.0 ? energy_kernel<true> : energy_kernel<false>;
+    const int rec = prof_begin(c, PH_ENERGY);
+    hipLaunchKernelGGL(k, dim3((unsigned)w.n_blocks, (unsigned)split), dim3(IB), 0, s, X, Y, Z,
+                       (const double *)c.st.mass, w, dst, bstride, c.eps * c.eps);
+    if ((e = hipGetLastError()) != hipSuccess || split == 1) {
+        prof_end(c, rec);
+        return e;
+    }
+    ForceOut out{};
+    out.pot = phi;
+    hipLaunchKernelGGL(reduce_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const double *)c.part, split, n, out, 1);
+    prof_end(c, rec);
     return hipGetLastError();
 }
 

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(TPB) void energy_partial(State st, int64_t n, const
         const double x = st.pos[i], y = st.pos[n + i], z = st.pos[2 * n + i];
         const double vx = st.vel[i], vy = st.vel[n + i], vz = st.vel[2 * n + i];
         q[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
-        q[1] = m * phi[i];   // phi[i] = -sum_{j > i} m_j / r_ij
+        q[1] = m * phi[i];   // phi[i] = -sum of m_j / r_ij over the half-window of i
         q[2] = m * (y * vz - z * vy);
         q[3] = m * (z * vx - x * vz);
         q[4] = m * (x * vy - y * vx);

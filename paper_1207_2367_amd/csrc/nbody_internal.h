@@ -72,6 +72,7 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
 // start-up evaluation (FP64, a, da, d2a and crackle of every particle from
 // the stored state): split = 1, results written straight to out
+hipError_t launch_energy_pot(Ctx &c, double *phi, hipStream_t s);
 hipError_t launch_force_init(Ctx &c, const ForceWork &w, const Launch &L,
                              const ForceOut &out, hipStream_t s);
 int64_t iblock_size(const Launch &L);

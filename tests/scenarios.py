@@ -10,6 +10,7 @@ benchmark).  Test infrastructure: not collected by pytest, run by hand:
     python tests/scenarios.py plummer8m      # 8M sources x 65,536 active
     python tests/scenarios.py bfactor16k     # split-source on/off vs N_act
     python tests/scenarios.py etascan        # energy error against eta
+    python tests/scenarios.py etascan:32768:mixed   # one size, one path
 """
 from __future__ import annotations
 
@@ -240,7 +241,10 @@ def king256(t_end=1.0):
         it = oracle.Integrator(m[sl], x[sl], v[sl], 1e-4)
         it.init(t_end)
         o0 = sum(it.energy()[:2])
-        it.run(t_end)
+        for k in range(1, 17):   # in pieces, so that a long run keeps printing
+            it.run(t_end * k / 16)
+            if sizes[c] > 4000:
+                _log(f"  king256 oracle cluster {c} (n = {sizes[c]}): t = {t_end * k / 16}")
         o1 = sum(it.energy()[:2])
         g = System(m[sl], x[sl], v[sl], 1e-4, precision=PREC_MIXED)
         g0 = sum(g.energy()[:2])
@@ -248,6 +252,7 @@ def king256(t_end=1.0):
         g1 = sum(g.energy()[:2])
         per.append({"cluster": int(c), "n": int(sizes[c]), "oracle_dE_over_E": (o1 - o0) / o0,
                     "gpu_mixed_dE_over_E": (g1 - g0) / g0})
+        _log(f"  king256 cluster {per[-1]}")
     res["per_cluster"] = per
     return res
 
@@ -324,17 +329,20 @@ def bfactor16k(n=16384):
     return {"config": "bfactor16k", "n": n, "rows": rows}
 
 
-def etascan(ns=(1 << 15, 1 << 16), etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_end=10.0):
+def etascan(n=None, precs="mixed,fp64", etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_end=10.0):
     """Energy and angular-momentum error against eta (the paper's Fig. 1
-    experiment): Plummer spheres, 10 time units, the paper's average of the
-    relative errors at t = 1 .. 10, both the mixed and the FP64 paths."""
+    experiment): Plummer spheres of 2^15 and 2^16 bodies (or n), 10 time
+    units, the paper's average of the relative errors at t = 1 .. 10, the
+    mixed and the FP64 paths (or the comma-separated list precs)."""
     import ics
     from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, NBodyError, System
+    ns = (1 << 15, 1 << 16) if n is None else (int(n),)
+    modes = [(p, {"mixed": PREC_MIXED, "fp64": PREC_FP64}[p]) for p in precs.split(",")]
     rows = []
     for n in ns:
         m, x, v = ics.plummer(n, 7000 + n % 997)
         for eta in etas:
-            for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
+            for name, prec in modes:
                 s = System(m, x, v, 1e-4, precision=prec, eta=eta)
                 ek, ep, L = s.energy()
                 e0, l0 = ek + ep, np.linalg.norm(L)
@@ -347,6 +355,8 @@ def etascan(ns=(1 << 15, 1 << 16), etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_end=1
                         ek, ep, L = s.energy()
                         de.append(abs((ek + ep - e0) / e0))
                         dl.append(abs((np.linalg.norm(L) - l0) / l0))
+                        _log(f"  n {n} eta {eta} {name}: t = {t}, {steps} block steps, "
+                             f"dE/E {de[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
                     err = None
                 except NBodyError as e:
                     err = str(e)
@@ -373,7 +383,9 @@ def _default(o):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:]:
-        _log(f"scenario {name}")
-        out = RUNS[name]()
+    # each argument: NAME or NAME:ARG[:ARG...] (positional arguments of the run)
+    for spec in sys.argv[1:]:
+        name, *args = spec.split(":")
+        _log(f"scenario {spec}")
+        out = RUNS[name](*args)
         print(json.dumps(out, default=_default), flush=True)

@@ -222,8 +222,14 @@ def test_plummer_1024_to_t1_energy():
     assert abs(de32) < 1e-7
 
 
-def test_energy_parity_and_clusters():
-    m, x, v, off = ics.king_ensemble(4, sizes=[700, 300, 1500, 256])
+@pytest.mark.parametrize("sizes", [[700, 300, 1500, 256], [5077], [4096], [3000, 1, 2100, 2]],
+                         ids=["king4", "odd5077", "even4096", "split_clusters"])
+def test_energy_parity_and_clusters(sizes):
+    """Energy and angular momentum (Sect. 5.1) against the oracle: odd and
+    even cluster sizes (the two window rules of the energy pass), clusters
+    of one and two bodies, and sizes that split the pass over workgroups."""
+    m, x, v, off = ics.king_ensemble(len(sizes), sizes=sizes)
+    log_case(test="energy", sizes=sizes)
     for prec in (0, 1):
         s = _system(m, x, v, prec, offsets=off)
         ek, ep, L = s.energy()
