@@ -153,6 +153,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     uint64_t *tmin = (uint64_t *)take(nc * 8);
     double *tblock = (double *)take(nc * d);
     int32_t *ch_cnt = (int32_t *)take(n_chunks_max * 4);
+    uint64_t *ch_min = (uint64_t *)take(n_chunks_max * 8);
     int64_t *ch_pos = (int64_t *)take(n_chunks_max * 8);
     int64_t *seg = (int64_t *)take((nc + 1) * 8);
     int32_t *blk_cl = (int32_t *)take((n + nc + 1) * 4);
@@ -177,6 +178,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
         c->d_tmin = tmin;
         c->d_tblock = tblock;
         c->d_chunk_cnt = ch_cnt;
+        c->d_chunk_min = ch_min;
         c->d_chunk_pos = ch_pos;
         c->d_seg = seg;
         c->d_blk_cluster = blk_cl;

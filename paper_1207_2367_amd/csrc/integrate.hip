@@ -143,66 +143,64 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     return v;
 }
 
-// per chunk: min over its particles of t + dt (as ordered bits; times are
-// >= 0 so the IEEE bits order like the values), into the cluster's slot
+// per chunk: the minimum over its particles of t + dt (as ordered bits;
+// times are >= 0 so the IEEE bits order like the values) and how many of
+// its particles reach it; the minimum also goes into the cluster's slot.
+// A chunk's particles are due exactly when its minimum is the cluster's.
+__device__ __forceinline__ void min_count(uint64_t &v, int &n, uint64_t ov, int on)
+{
+    if (ov < v) {
+        v = ov;
+        n = on;
+    } else if (ov == v) {
+        n += on;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void sched_min(const double *t, const double *dt,
                                                  const int64_t *chunk_begin,
-                                                 const int32_t *chunk_cluster, uint64_t *tmin)
+                                                 const int32_t *chunk_cluster, uint64_t *tmin,
+                                                 uint64_t *cmin, int32_t *ccnt)
 {
-    __shared__ uint64_t red[TPB / 64];
+    __shared__ uint64_t rv[TPB / 64];
+    __shared__ int rn[TPB / 64];
     const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
     uint64_t v = ~0ull;
-    for (int64_t i = b + threadIdx.x; i < e; i += TPB) {
-        const uint64_t u = (uint64_t)__double_as_longlong(t[i] + dt[i]);
-        v = u < v ? u : v;
+    int n = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += TPB)
+        min_count(v, n, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
+    // xor butterfly: both partners form the same (min, count) of their union
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t ov = __shfl_xor(v, m, 64);
+        const int on = __shfl_xor(n, m, 64);
+        min_count(v, n, ov, on);
     }
-    v = wave_min_u64(v);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) {
+        rv[threadIdx.x >> 6] = v;
+        rn[threadIdx.x >> 6] = n;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t m = red[0];
         for (int w = 1; w < TPB / 64; ++w)
-            m = red[w] < m ? red[w] : m;
-        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)m);
+            min_count(v, n, rv[w], rn[w]);
+        cmin[blockIdx.x] = v;
+        ccnt[blockIdx.x] = n;
+        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)v);
     }
 }
 
 __device__ __forceinline__ bool due(double t, double dt, double T) { return t + dt == T; }
 
-__global__ __launch_bounds__(TPB) void sched_count(const double *t, const double *dt,
-                                                   const int64_t *chunk_begin,
-                                                   const int32_t *chunk_cluster,
-                                                   const uint64_t *tmin, double t_target,
-                                                   int32_t *cnt)
-{
-    __shared__ int red[TPB / 64];
-    const double T = __longlong_as_double((long long)tmin[chunk_cluster[blockIdx.x]]);
-    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
-    int c = 0;
-    if (T <= t_target)
-        for (int64_t i = b + threadIdx.x; i < e; i += TPB)
-            c += due(t[i], dt[i], T) ? 1 : 0;
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        c += __shfl_xor(c, m, 64);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int w = 0; w < TPB / 64; ++w)
-            s += red[w];
-        cnt[blockIdx.x] = s;
-    }
-}
-
-// Single workgroup: exclusive scan of the chunk counts (chunks are in
-// particle order, so clusters are contiguous), per-cluster active
-// segments and block times, totals and the N_act histogram.
+// Single workgroup: the due count of every chunk (its count at its minimum
+// when that is its cluster's block time and the cluster is not past the
+// target), their exclusive scan (chunks are in particle order, so clusters
+// are contiguous), per-cluster active segments and block times, totals and
+// the N_act histogram.
 // info[0] = N_act total, info[1] = bits of the earliest block time,
 // info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot.
-__global__ __launch_bounds__(1024) void sched_scan(const int32_t *cnt, int64_t n_chunks,
+__global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
+                                                   int64_t n_chunks,
                                                    const int32_t *chunk_cluster,
                                                    const uint64_t *tmin, const int64_t *off,
                                                    int32_t nc, double t_target,
@@ -217,7 +215,12 @@ __global__ __launch_bounds__(1024) void sched_scan(const int32_t *cnt, int64_t n
     __syncthreads();
     for (int64_t base = 0; base < n_chunks; base += 1024) {
         const int64_t q = base + threadIdx.x;
-        const int64_t v = q < n_chunks ? cnt[q] : 0;
+        int64_t v = 0;
+        if (q < n_chunks) {
+            const uint64_t T = tmin[chunk_cluster[q]];
+            if (cmin[q] == T && __longlong_as_double((long long)T) <= t_target)
+                v = ccnt[q];
+        }
         buf[threadIdx.x] = v;
         __syncthreads();
         for (int s = 1; s < 1024; s <<= 1) {
@@ -239,26 +242,47 @@ __global__ __launch_bounds__(1024) void sched_scan(const int32_t *cnt, int64_t n
         if (q == 0 || chunk_cluster[q - 1] != c)
             seg[c] = chunk_pos[q];
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
         seg[nc] = carry;
         info[0] = carry;
-        double tmn = INFINITY;
-        int64_t pairs = 0;
-        for (int32_t c = 0; c < nc; ++c) {
-            const double T = __longlong_as_double((long long)tmin[c]);
-            const bool act = T <= t_target;
-            tblock[c] = act ? T : INFINITY;
-            if (act && T < tmn)
-                tmn = T;
-            const int64_t na = seg[c + 1] - seg[c];
-            pairs += na * (off[c + 1] - off[c]);
-            if (na > 0) {
-                int bb = 0;
-                while ((int64_t(1) << (bb + 1)) <= na)
-                    ++bb;
-                hist[bb] += 1;
-            }
+    }
+    __syncthreads();
+    // per cluster (spread over the threads): block time, interactions and
+    // the histogram; then the earliest time and the pair total
+    __shared__ double rmin[1024 / 64];
+    __shared__ int64_t rsum[1024 / 64];
+    double tmn = INFINITY;
+    int64_t pairs = 0;
+    for (int32_t c = threadIdx.x; c < nc; c += 1024) {
+        const double T = __longlong_as_double((long long)tmin[c]);
+        const bool act = T <= t_target;
+        tblock[c] = act ? T : INFINITY;
+        if (act && T < tmn)
+            tmn = T;
+        const int64_t na = seg[c + 1] - seg[c];
+        pairs += na * (off[c + 1] - off[c]);
+        if (na > 0) {
+            int bb = 0;
+            while ((int64_t(1) << (bb + 1)) <= na)
+                ++bb;
+            atomicAdd((unsigned long long *)&hist[bb], 1ull);
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const double o = __shfl_xor(tmn, m, 64);
+        tmn = o < tmn ? o : tmn;
+        pairs += __shfl_xor(pairs, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rmin[threadIdx.x >> 6] = tmn;
+        rsum[threadIdx.x >> 6] = pairs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / 64; ++w) {
+            tmn = rmin[w] < tmn ? rmin[w] : tmn;
+            pairs += rsum[w];
         }
         info[1] = __double_as_longlong(tmn);
         info[2] = pairs;
@@ -589,13 +613,10 @@ hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
     hipLaunchKernelGGL(sched_min, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
-                       c.d_tmin);
-    hipLaunchKernelGGL(sched_count, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
-                       (const double *)c.st.t, (const double *)c.st.dt,
-                       (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
-                       (const uint64_t *)c.d_tmin, t_target, c.d_chunk_cnt);
-    hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const int32_t *)c.d_chunk_cnt,
-                       c.n_chunks, (const int32_t *)c.d_chunk_cluster,
+                       c.d_tmin, c.d_chunk_min, c.d_chunk_cnt);
+    hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const uint64_t *)c.d_chunk_min,
+                       (const int32_t *)c.d_chunk_cnt, c.n_chunks,
+                       (const int32_t *)c.d_chunk_cluster,
                        (const uint64_t *)c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
                        c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info, c.d_info + 8,
                        (const uint32_t *)c.d_err);

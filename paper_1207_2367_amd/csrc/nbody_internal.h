@@ -142,7 +142,8 @@ struct Ctx {
     int64_t *d_chunk_begin = nullptr;    // [n_chunks + 1]
     uint64_t *d_tmin = nullptr;          // [nc] bits of min(t+dt), per cluster
     double *d_tblock = nullptr;          // [nc] block time, +inf if done
-    int32_t *d_chunk_cnt = nullptr;      // [n_chunks]
+    int32_t *d_chunk_cnt = nullptr;      // [n_chunks] particles at the chunk's minimum
+    uint64_t *d_chunk_min = nullptr;     // [n_chunks] chunk minimum of t + dt (bits)
     int64_t *d_chunk_pos = nullptr;      // [n_chunks]
     int64_t *d_seg = nullptr;            // [nc + 1] active segments
     int32_t *d_blk_cluster = nullptr;    // [n / 1 + nc] i-block -> cluster
