@@ -151,6 +151,23 @@ def _hist_groups(hist):
     return out
 
 
+def _by_log2(na_log, pr_log, ms_log):
+    """Evaluation launches grouped by floor(log2 N_act): count, pairs, time,
+    rate (the efficiency of the batched launches by block size)."""
+    out = {}
+    for na, pr, ms in zip(na_log, pr_log, ms_log):
+        if na <= 0:
+            continue
+        b = int(math.log2(na))
+        o = out.setdefault(b, [0, 0.0, 0.0])
+        o[0] += 1
+        o[1] += float(pr)
+        o[2] += float(ms)
+    return {f"2^{b}": {"launches": o[0], "pairs": o[1], "ms": o[2],
+                       "G_per_s": o[1] / (o[2] * 1e-3) / 1e9 if o[2] > 0 else None}
+            for b, o in sorted(out.items())}
+
+
 def plummer1m(t_end=0.125, n=1 << 20):
     """1M-body Plummer sphere (seed 3003), eps 1e-4, eta 0.45, to t = 0.125:
     mixed and FP64 paths, energy error, block N_act histogram, throughput,
@@ -228,10 +245,12 @@ def king256(t_end=1.0):
     e0 = sum(s.energy()[:2])
     st, wall, prof = _run(s, t_end, pieces=16)
     e1 = sum(s.energy()[:2])
+    na_log, pr_log, ms_log = s.force_log()
     res["mixed"] = {"dE_over_E_total": (e1 - e0) / e0, "block_steps": st["block_steps"],
                     "interactions": st["interactions"], "wall_s": wall,
                     "G_interactions_per_s": st["interactions"] / wall / 1e9,
-                    "phase_ms": {k: v[0] for k, v in prof.items() if k != "pairs"}}
+                    "phase_ms": {k: v[0] for k, v in prof.items() if k != "pairs"},
+                    "evaluation_by_log2_n_act": _by_log2(na_log, pr_log, ms_log)}
     # oracle on the 8 smallest + 4 seeded-random clusters, and the GPU on
     # the same clusters alone
     pick = list(np.argsort(sizes)[:8]) + list(np.random.default_rng(4200).choice(sizes.size, 4, replace=False))
