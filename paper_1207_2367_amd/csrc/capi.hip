@@ -262,9 +262,9 @@ int64_t max_cluster(const Ctx &c)
 
 // force of the active slots described by c.d_seg (and idx) into out
 int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, const ForceOut &out,
-              double pairs_hint = -1.0)
+              double pairs_hint = -1.0, int64_t n_src = -1)
 {
-    Launch L = pick_launch(c, n_act_typ, max_cluster(c));
+    Launch L = pick_launch(c, n_act_typ, n_src > 0 ? n_src : max_cluster(c));
     while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
         L.split >>= 1;
     const int64_t ib = iblock_size(L);
@@ -339,11 +339,20 @@ int run_force_init(Ctx &c)
 int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
                nbody_step_stats *stats)
 {
+    // the host needs N_act (and the block time) to size the evaluation; it
+    // waits for the copy of the scan's totals only, while the GPU goes on
+    // with the compaction of the active list and the predictor (which skips
+    // clusters past the target, so it is harmless when nothing is due)
     int rec = prof_begin(c, PH_SCHED);
-    HIPCHK(c, launch_schedule(c, t_target, c.stream));
-    prof_end(c, rec);
+    HIPCHK(c, launch_sched_head(c, t_target, c.stream));
     HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(c, hipStreamSynchronize(c.stream));
+    HIPCHK(c, hipEventRecord(c.ev_info, c.stream));
+    HIPCHK(c, launch_sched_scatter(c, c.stream));
+    prof_end(c, rec);
+    rec = prof_begin(c, PH_PREDICT);
+    HIPCHK(c, launch_pack(c, c.d_tblock, 0, c.d_cluster_of, c.stream));
+    prof_end(c, rec);
+    HIPCHK(c, hipEventSynchronize(c.ev_info));
     const int64_t n_act = c.h_info[0];
     double tb;
     std::memcpy(&tb, &c.h_info[1], 8);
@@ -353,9 +362,6 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     *t_block_out = tb;
     if (n_act == 0)
         return NBODY_OK;
-    rec = prof_begin(c, PH_PREDICT);
-    HIPCHK(c, launch_pack(c, c.d_tblock, 0, c.d_cluster_of, c.stream));
-    prof_end(c, rec);
     ForceOut out{};
     out.vec[0] = c.fnew;
     out.vec[1] = c.fnew + 3 * n_act;
@@ -363,10 +369,10 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     out.pot = nullptr;
     out.sk = 1;
     out.sd = n_act;
-    int64_t active_clusters = 0;
-    (void)active_clusters;
-    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / c.nc);
-    int rc = run_force(c, c.act, n_act, typ, out, (double)c.h_info[2]);
+    // launch shape from the typical active set of the clusters that have
+    // one, against the largest of them
+    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / std::max<int64_t>(1, c.h_info[4]));
+    int rc = run_force(c, c.act, n_act, typ, out, (double)c.h_info[2], c.h_info[5]);
     if (rc)
         return rc;
     rec = prof_begin(c, PH_CORRECT);
@@ -457,6 +463,8 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     c.cfg.cluster_offsets = nullptr;
     c.stream = (hipStream_t)cfg->stream;
     auto bail = [&](int rc) {
+        if (c.ev_info)
+            (void)hipEventDestroy(c.ev_info);
         if (c.h_info)
             (void)hipHostFree(c.h_info);
         delete h;
@@ -470,6 +478,8 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
         return bail(NBODY_EDEVICE);
     c.h_red = reinterpret_cast<double *>(c.h_info + 64);
     c.h_err = reinterpret_cast<uint32_t *>(c.h_red + 64);
+    if (hipEventCreateWithFlags(&c.ev_info, hipEventDisableTiming) != hipSuccess)
+        return bail(NBODY_EDEVICE);
     // cluster offsets, cluster of each particle, schedule chunk table
     c.off.assign(nc + 1, 0);
     if (nc > 1)
@@ -503,6 +513,7 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     }
     H(hipMemsetAsync(c.d_err, 0, 4, s), "err");
     H(hipMemsetAsync(c.d_info, 0, 64 * 8, s), "info");
+    H(launch_sched_reset(c, s), "sched");   // the scan keeps them reset afterwards
     H(hipMemcpyAsync(c.st.mass, d_mass, n * 8, hipMemcpyDeviceToDevice, s), "mass");
     H(launch_aos_to_soa(d_pos, c.st.pos, n, s), "pos");
     H(launch_aos_to_soa(d_vel, c.st.vel, n, s), "vel");
@@ -544,6 +555,8 @@ void nbody_free(nbody_ctx *ctx)
     (void)prof_collect(ctx->c);
     for (hipEvent_t e : ctx->c.prof_pool)
         (void)hipEventDestroy(e);
+    if (ctx->c.ev_info)
+        (void)hipEventDestroy(ctx->c.ev_info);
     if (ctx->c.h_info)
         (void)hipHostFree(ctx->c.h_info);
     delete ctx;
@@ -771,6 +784,12 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
     if (!(max_ms > 0.0))
         max_ms = 200.0;
     const int64_t nsrc = max_cluster(c);
+    size_t big = 0;
+    for (size_t k = 0; k + 1 < c.off.size(); ++k)
+        if (c.off[k + 1] - c.off[k] == nsrc) {
+            big = k;
+            break;
+        }
     hipStream_t s = c.stream;
     // sources = the stored state; outputs to the integrator's scratch
     HIPCHK(c, launch_pack(c, nullptr, 1, nullptr, s));
@@ -788,10 +807,10 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
     for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc &&
                     (int64_t(1) << b) * nsrc <= (int64_t(1) << 35); ++b) {
         const int64_t na = int64_t(1) << b;
-        // evenly spread active particles of the first cluster
+        // evenly spread active particles of the largest cluster
         hidx.resize(na);
         for (int64_t k = 0; k < na; ++k)
-            hidx[k] = (int32_t)(c.off[0] + k * nsrc / na);
+            hidx[k] = (int32_t)(c.off[big] + k * nsrc / na);
         if (hipMemcpyAsync(c.act, hidx.data(), na * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = hip_fail(c, hipGetLastError(), "autotune copy");

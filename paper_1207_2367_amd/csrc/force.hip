@@ -583,9 +583,8 @@ int ilog2(int64_t v)
 
 int64_t iblock_size(const Launch &L) { return (int64_t)L.waves * (64 / L.lpi); }
 
-// Heuristic launch shape (used until the autotuner has measured): enough
-// lanes to give every SIMD of the 256 CUs several waves, preferring the
-// split-source factor (coarse, cheap) and then lanes per particle.
+// Launch shape: the pinned one, else the autotuner's for this power of two
+// of N_act, else a rule (below).
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
 {
     if (c.pinned.lpi > 0)
@@ -594,30 +593,29 @@ Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
         const int b = ilog2(n_act);
         if (b < (int)c.tuned.size() && c.tuned[b].lpi > 0) {
             Launch L = c.tuned[b];
-            while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
+            // at least one tile per split of the largest source range, and
+            // the partials within the split buffer
+            while (L.split > 1 && ((int64_t)L.split * n_act > c.part_cap ||
+                                   n_src / L.split < 64 * L.waves))
                 L.split >>= 1;
             return L;
         }
     }
+    // Rule fitted to the autotuner's choices on 16,384- and 65,536-source
+    // spheres: 4 waves; about 4096 lanes per split (lanes per particle
+    // 4096 / N_act, between 1 and 64); then split the sources while every
+    // split keeps two tiles and the grid stays within 2^19 lanes.
     Launch L;
     L.waves = 4;
     L.lpi = 1;
     L.split = 1;
-    const int64_t want_lanes = int64_t(256) * 4 * 64 * 8;  // 8 waves per SIMD
-    if (n_act < 256) {
-        L.waves = 1;
-    }
-    // lanes per particle first for tiny active sets, so that a wave is full
-    while (n_act * L.lpi < 64 * L.waves && L.lpi < 64)
+    while (n_act * L.lpi < 4096 && L.lpi < 64)
         L.lpi <<= 1;
     const int64_t nt = 64 * L.waves;
-    auto lanes = [&](const Launch &q) { return n_act * q.lpi * q.split; };
-    // then split sources while every split keeps >= 4 tiles
-    while (lanes(L) < want_lanes && n_src / ((int64_t)L.split * 2) >= 4 * nt &&
+    const int64_t max_lanes = int64_t(1) << 19;
+    while (n_act * L.lpi * L.split * 2 <= max_lanes && n_src / ((int64_t)L.split * 2) >= 2 * nt &&
            (int64_t)L.split * 2 * n_act <= c.part_cap)
         L.split <<= 1;
-    while (lanes(L) < want_lanes && L.lpi < 64)
-        L.lpi <<= 1;
     return L;
 }
 

@@ -198,11 +198,12 @@ __device__ __forceinline__ bool due(double t, double dt, double T) { return t + 
 // are contiguous), per-cluster active segments and block times, totals and
 // the N_act histogram.
 // info[0] = N_act total, info[1] = bits of the earliest block time,
-// info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot.
+// info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot,
+// info[4] = clusters with active particles, info[5] = the largest of them.
 __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
                                                    int64_t n_chunks,
                                                    const int32_t *chunk_cluster,
-                                                   const uint64_t *tmin, const int64_t *off,
+                                                   uint64_t *tmin, const int64_t *off,
                                                    int32_t nc, double t_target,
                                                    int64_t *chunk_pos, int64_t *seg,
                                                    double *tblock, int64_t *info,
@@ -250,9 +251,9 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
     // per cluster (spread over the threads): block time, interactions and
     // the histogram; then the earliest time and the pair total
     __shared__ double rmin[1024 / 64];
-    __shared__ int64_t rsum[1024 / 64];
+    __shared__ int64_t rsum[1024 / 64], rcnt[1024 / 64], rbig[1024 / 64];
     double tmn = INFINITY;
-    int64_t pairs = 0;
+    int64_t pairs = 0, nclus = 0, big = 0;
     for (int32_t c = threadIdx.x; c < nc; c += 1024) {
         const double T = __longlong_as_double((long long)tmin[c]);
         const bool act = T <= t_target;
@@ -260,8 +261,11 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
         if (act && T < tmn)
             tmn = T;
         const int64_t na = seg[c + 1] - seg[c];
-        pairs += na * (off[c + 1] - off[c]);
+        const int64_t nsrc = off[c + 1] - off[c];
+        pairs += na * nsrc;
         if (na > 0) {
+            ++nclus;
+            big = nsrc > big ? nsrc : big;
             int bb = 0;
             while ((int64_t(1) << (bb + 1)) <= na)
                 ++bb;
@@ -273,20 +277,33 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
         const double o = __shfl_xor(tmn, m, 64);
         tmn = o < tmn ? o : tmn;
         pairs += __shfl_xor(pairs, m, 64);
+        nclus += __shfl_xor(nclus, m, 64);
+        const int64_t ob = __shfl_xor(big, m, 64);
+        big = ob > big ? ob : big;
     }
     if ((threadIdx.x & 63) == 0) {
         rmin[threadIdx.x >> 6] = tmn;
         rsum[threadIdx.x >> 6] = pairs;
+        rcnt[threadIdx.x >> 6] = nclus;
+        rbig[threadIdx.x >> 6] = big;
     }
     __syncthreads();
+    // every read of the per-cluster minima is done: leave them reset for the
+    // next schedule (so that no separate reset launch is needed)
+    for (int32_t c = threadIdx.x; c < nc; c += 1024)
+        tmin[c] = ~0ull;
     if (threadIdx.x == 0) {
         for (int w = 1; w < 1024 / 64; ++w) {
             tmn = rmin[w] < tmn ? rmin[w] : tmn;
             pairs += rsum[w];
+            nclus += rcnt[w];
+            big = rbig[w] > big ? rbig[w] : big;
         }
         info[1] = __double_as_longlong(tmn);
         info[2] = pairs;
         info[3] = (int64_t)*err;
+        info[4] = nclus;
+        info[5] = big;
     }
 }
 
@@ -607,9 +624,16 @@ hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel, 
     return hipGetLastError();
 }
 
-hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
+hipError_t launch_sched_reset(const Ctx &c, hipStream_t s)
 {
     hipLaunchKernelGGL(sched_reset, dim3(nblk(c.nc)), dim3(TPB), 0, s, c.d_tmin, c.nc);
+    return hipGetLastError();
+}
+
+// minima, counts and scan: block times, segments, N_act (info) -- the
+// per-cluster minima must be reset (at init, and by every scan after use)
+hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s)
+{
     hipLaunchKernelGGL(sched_min, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
@@ -617,14 +641,26 @@ hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
     hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const uint64_t *)c.d_chunk_min,
                        (const int32_t *)c.d_chunk_cnt, c.n_chunks,
                        (const int32_t *)c.d_chunk_cluster,
-                       (const uint64_t *)c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
+                       c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
                        c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info, c.d_info + 8,
                        (const uint32_t *)c.d_err);
+    return hipGetLastError();
+}
+
+// ordered list of the due particles
+hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s)
+{
     hipLaunchKernelGGL(sched_scatter, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
                        (const double *)c.d_tblock, (const int64_t *)c.d_chunk_pos, c.act);
     return hipGetLastError();
+}
+
+hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
+{
+    hipError_t e = launch_sched_head(c, t_target, s);
+    return e != hipSuccess ? e : launch_sched_scatter(c, s);
 }
 
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s)

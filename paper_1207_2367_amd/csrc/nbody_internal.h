@@ -83,6 +83,9 @@ hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
 hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel,
                               double *acc, hipStream_t s);
 hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_sched_reset(const Ctx &c, hipStream_t s);
+hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s);
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
 hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
@@ -161,6 +164,7 @@ struct Ctx {
     bool prof = false;
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
+    hipEvent_t ev_info = nullptr;        // recorded after the schedule's host copy
     double prof_ms[PH_N] = {0};
     int64_t prof_cnt[PH_N] = {0};
     double prof_pairs = 0.0;

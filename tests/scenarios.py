@@ -11,6 +11,7 @@ benchmark).  Test infrastructure: not collected by pytest, run by hand:
     python tests/scenarios.py bfactor16k     # split-source on/off vs N_act
     python tests/scenarios.py etascan        # energy error against eta
     python tests/scenarios.py etascan:32768:mixed   # one size, one path
+    python tests/scenarios.py blocks32k      # where a small-block run spends its time
 """
 from __future__ import annotations
 
@@ -388,9 +389,40 @@ def etascan(n=None, precs="mixed,fp64", etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_
     return {"config": "etascan", "rows": rows}
 
 
+def blocks32k(n=32768, t_end=1.0):
+    """Where the time of a small-block integration goes: a 32,768-body
+    Plummer sphere (seed 7000 + n % 997, eta 0.45) to t = 1 with the phase
+    profile; per block step: wall time, GPU time by phase, evaluation
+    efficiency by N_act."""
+    import ics
+    from paper_1207_2367_amd import PREC_MIXED, System
+    n = int(n)
+    m, x, v = ics.plummer(n, 7000 + n % 997)
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+    st0, wall0, _ = _run(s, float(t_end), profile=False, pieces=4)
+    # the same run again with the event timing of every phase (which adds
+    # host work of its own)
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+    st, wall, prof = _run(s, float(t_end), pieces=4)
+    na_log, pr_log, ms_log = s.force_log()
+    steps = st["block_steps"]
+    phase_ms = {k: v[0] for k, v in prof.items() if k != "pairs"}
+    # and with autotuned launch shapes instead of the rule
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+    s.autotune(50.0)
+    st2, wall2, _ = _run(s, float(t_end), profile=False, pieces=4)
+    return {"config": "blocks32k", "n": n, "block_steps": steps, "wall_s": wall0,
+            "wall_s_autotuned": wall2, "block_steps_autotuned": st2["block_steps"],
+            "wall_s_profiled": wall, "interactions": st["interactions"],
+            "us_per_block_step": wall0 / st0["block_steps"] * 1e6,
+            "gpu_us_per_block_step_by_phase": {k: v / steps * 1e3 for k, v in phase_ms.items()},
+            "launches_by_phase": {k: v[1] for k, v in prof.items() if k != "pairs"},
+            "evaluation_by_log2_n_act": _by_log2(na_log, pr_log, ms_log)}
+
+
 RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
         "king256": king256, "plummer8m": plummer8m, "bfactor16k": bfactor16k,
-        "etascan": etascan}
+        "etascan": etascan, "blocks32k": blocks32k}
 
 
 def _default(o):
