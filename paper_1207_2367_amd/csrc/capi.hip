@@ -344,8 +344,7 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     // with the compaction of the active list and the predictor (which skips
     // clusters past the target, so it is harmless when nothing is due)
     int rec = prof_begin(c, PH_SCHED);
-    HIPCHK(c, launch_sched_head(c, t_target, c.stream));
-    HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, launch_sched_head(c, t_target, c.stream));   // totals also into h_tot
     HIPCHK(c, hipEventRecord(c.ev_info, c.stream));
     HIPCHK(c, launch_sched_scatter(c, c.stream));
     prof_end(c, rec);
@@ -353,10 +352,12 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     HIPCHK(c, launch_pack(c, c.d_tblock, 0, c.d_cluster_of, c.stream));
     prof_end(c, rec);
     HIPCHK(c, hipEventSynchronize(c.ev_info));
-    const int64_t n_act = c.h_info[0];
+    int64_t tot[8];
+    std::memcpy(tot, c.h_tot, sizeof tot);
+    const int64_t n_act = tot[0];
     double tb;
-    std::memcpy(&tb, &c.h_info[1], 8);
-    if (c.h_info[3] != 0)
+    std::memcpy(&tb, &tot[1], 8);
+    if (tot[3] != 0)
         return take_err(c);
     *n_act_out = n_act;
     *t_block_out = tb;
@@ -371,8 +372,8 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     out.sd = n_act;
     // launch shape from the typical active set of the clusters that have
     // one, against the largest of them
-    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / std::max<int64_t>(1, c.h_info[4]));
-    int rc = run_force(c, c.act, n_act, typ, out, (double)c.h_info[2], c.h_info[5]);
+    const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / std::max<int64_t>(1, tot[4]));
+    int rc = run_force(c, c.act, n_act, typ, out, (double)tot[2], tot[5]);
     if (rc)
         return rc;
     rec = prof_begin(c, PH_CORRECT);
@@ -382,7 +383,7 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     if (stats) {
         stats->block_steps += 1;
         stats->active_total += n_act;
-        stats->interactions += (double)c.h_info[2];
+        stats->interactions += (double)tot[2];
     }
     return NBODY_OK;
 }
@@ -463,6 +464,8 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     c.cfg.cluster_offsets = nullptr;
     c.stream = (hipStream_t)cfg->stream;
     auto bail = [&](int rc) {
+        if (c.h_tot)
+            (void)hipHostFree(c.h_tot);
         if (c.ev_info)
             (void)hipEventDestroy(c.ev_info);
         if (c.h_info)
@@ -480,6 +483,11 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     c.h_err = reinterpret_cast<uint32_t *>(c.h_red + 64);
     if (hipEventCreateWithFlags(&c.ev_info, hipEventDisableTiming) != hipSuccess)
         return bail(NBODY_EDEVICE);
+    if (hipHostMalloc((void **)&c.h_tot, 8 * sizeof(int64_t),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c.d_tot, c.h_tot, 0) != hipSuccess)
+        return bail(NBODY_EDEVICE);
+    std::memset(c.h_tot, 0, 8 * sizeof(int64_t));
     // cluster offsets, cluster of each particle, schedule chunk table
     c.off.assign(nc + 1, 0);
     if (nc > 1)
@@ -557,6 +565,8 @@ void nbody_free(nbody_ctx *ctx)
         (void)hipEventDestroy(e);
     if (ctx->c.ev_info)
         (void)hipEventDestroy(ctx->c.ev_info);
+    if (ctx->c.h_tot)
+        (void)hipHostFree(ctx->c.h_tot);
     if (ctx->c.h_info)
         (void)hipHostFree(ctx->c.h_info);
     delete ctx;

@@ -207,7 +207,8 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
                                                    int32_t nc, double t_target,
                                                    int64_t *chunk_pos, int64_t *seg,
                                                    double *tblock, int64_t *info,
-                                                   int64_t *hist, const uint32_t *err)
+                                                   int64_t *hist, const uint32_t *err,
+                                                   int64_t *info_host)
 {
     __shared__ int64_t buf[1024];
     __shared__ int64_t carry;
@@ -304,6 +305,16 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
         info[3] = (int64_t)*err;
         info[4] = nclus;
         info[5] = big;
+        if (info_host) {
+            // the same totals straight into host memory (mapped, coherent),
+            // read by the host once an event after this kernel has completed
+            info_host[0] = carry;
+            info_host[1] = __double_as_longlong(tmn);
+            info_host[2] = pairs;
+            info_host[3] = (int64_t)*err;
+            info_host[4] = nclus;
+            info_host[5] = big;
+        }
     }
 }
 
@@ -643,7 +654,7 @@ hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s)
                        (const int32_t *)c.d_chunk_cluster,
                        c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
                        c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info, c.d_info + 8,
-                       (const uint32_t *)c.d_err);
+                       (const uint32_t *)c.d_err, c.d_tot);
     return hipGetLastError();
 }
 

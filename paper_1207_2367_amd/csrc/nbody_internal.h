@@ -158,6 +158,8 @@ struct Ctx {
     double *d_phi = nullptr;             // [n] potential scratch (energy)
     // host pinned mirror for small readbacks
     int64_t *h_info = nullptr;
+    int64_t *h_tot = nullptr;            // [8] scheduler totals, written by the GPU (mapped)
+    int64_t *d_tot = nullptr;            // device address of h_tot
     double *h_red = nullptr;
     uint32_t *h_err = nullptr;
     // profiling
