@@ -51,7 +51,8 @@ extern "C" {
    FP32PAIR: every pair term in FP32 (from the FP64 difference r_j - r_i)
      with compensated accumulation -- fastest; safe only where steps stay
      near their natural length.
-   FP64: every operation in FP64 (comparison path).                      */
+   FP64: every operation in FP64 (comparison path; 1/r from the FP32
+     rsqrt seed refined to FP64 accuracy by one third-order step).       */
 #define NBODY_PREC_MIXED 0
 #define NBODY_PREC_FP64 1
 #define NBODY_PREC_FP32PAIR 2
@@ -165,7 +166,10 @@ int nbody_correct(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx,
 /* One block time step of every cluster not yet at t_target (schedule,
    predict, evaluate, reduce, correct, new steps; paper Sect. 3 and Table
    1).  *n_act gets the number of particles advanced and *t_block the
-   earliest block time of the step.  Synchronizes.
+   earliest block time of the step.  Waits for the scheduler's totals
+   (the host sizes the evaluation from them); the evaluation and the
+   correction are then queued on the stream, so later calls on the same
+   stream see the completed step.
    Errors: EINVAL (t_target not a multiple of dt_min or < 0), EDEVICE,
    EDTMIN, ENONFINITE.                                                   */
 int nbody_block_step(nbody_ctx *ctx, double t_target, int64_t *n_act,
@@ -199,11 +203,12 @@ int nbody_set_state(nbody_ctx *ctx, const double *d_pos, const double *d_vel,
 int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3]);
 
 /* Measure launch shapes of the force kernel for active-set sizes
-   1, 2, 4, ... up to the largest cluster (sizes whose single launch would
-   exceed ~2^35 pairs keep the heuristic shape) and keep the fastest for
-   each size range in the context (the autotuner).  max_ms bounds the time
-   spent per size.  Uses the stored state as sources; does not change it.
-   Synchronizes.  Errors: EDEVICE.                                       */
+   1, 2, 4, ... up to the largest cluster, with active particles spread
+   over the largest cluster (sizes whose single launch would exceed ~2^35
+   pairs keep the launch rule), and keep the fastest for each size range
+   in the context (the autotuner).  Without it a fixed rule picks the
+   shape.  max_ms bounds the time spent per size.  Uses the stored state
+   as sources; does not change it.  Synchronizes.  Errors: EDEVICE.      */
 int nbody_autotune(nbody_ctx *ctx, double max_ms);
 
 /* Force kernel launch shape: lanes per active particle (1..64, a power of

@@ -120,7 +120,9 @@ __device__ __forceinline__ double pot_tile(const double *sx, const double *sy,
     return phi;
 }
 
-template <int PREC, int LPI, int NW, bool EPS0>
+// PHI: also sum the potential (nbody_force, the start-up pass); a block
+// step's evaluation does not need it (the energy has its own pass).
+template <int PREC, int LPI, int NW, bool EPS0, bool PHI>
 __global__ __launch_bounds__(NW * 64) void force_kernel(
     typename Smem<PREC>::R J, ForceWork w, ForceOut out, double *part,
     int64_t n_act_total, double eps2)
@@ -160,6 +162,11 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     const int64_t o0 = w.off[c], o1 = w.off[c + 1];
     int64_t chunk = (o1 - o0 + w.split - 1) / w.split;
     chunk = (chunk + NT - 1) / NT * NT;
+    // splits past this cluster's sources (chunks are whole tiles, so a small
+    // cluster fills fewer than B of them): nothing to do, and the reduction
+    // reads only the splits in use
+    if ((int64_t)b * chunk >= o1 - o0 && b > 0)
+        return;
     const int64_t j0 = o0 + (int64_t)b * chunk;
     const int64_t j1 = j0 + chunk < o1 ? j0 + chunk : o1;
 
@@ -242,7 +249,8 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                     if constexpr (EPS0)
                         rinv = r2 > 0.0f ? rinv : 0.0f;
                     const float mrinv = (float)s_m[t] * rinv;
-                    phi -= (double)mrinv;
+                    if constexpr (PHI)
+                        phi -= (double)mrinv;
                     const float rinv2 = rinv * rinv, mr3 = mrinv * rinv2;
                     const float dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
                     const float dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
@@ -274,7 +282,8 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
                 if constexpr (EPS0)
                     rinv = r2 > 0.0 ? rinv : 0.0;
                 const double mrinv = s_m[t] * rinv;
-                phi -= mrinv;
+                if constexpr (PHI)
+                    phi -= mrinv;
                 const double rinv2 = rinv * rinv;
                 const double mr3 = mrinv * rinv2;
                 if constexpr (MIXED) {
@@ -384,7 +393,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
         return;
     // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
     // potential: remove that term, computed with the same operations
-    if constexpr (!EPS0) {
+    if constexpr (!EPS0 && PHI) {
         if (i >= j0 && i < j1) {
             if constexpr (P32) {
                 const float e2f = (float)eps2;
@@ -510,10 +519,13 @@ __global__ __launch_bounds__(256) void energy_kernel(const double *X, const doub
 // active slot), so reads are coalesced over slots; the loads of 16 splits
 // are issued before their adds (the order of the adds is unchanged), which
 // keeps a tiny active set with a large B from waiting out B serial
-// round trips to L2.
+// round trips to L2.  With the evaluation's ForceWork (w.off != nullptr),
+// only the splits that hold sources of the slot's cluster are read (the
+// evaluation's chunks are whole tiles of nt sources).
 __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t B,
                                                     int64_t n_act, ForceOut out,
-                                                    int pot_only)
+                                                    int pot_only, ForceWork w,
+                                                    const int32_t *cluster_of, int nt)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int nq = pot_only ? 1 : 10;
@@ -522,6 +534,15 @@ __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t 
     const int q = pot_only ? 9 : (int)(t / n_act);
     const int64_t k = pot_only ? t : t - (int64_t)q * n_act;
     const double *p = part + (int64_t)q * n_act + k;
+    if (w.off) {
+        const int64_t i = w.idx ? (int64_t)w.idx[k] : k;
+        const int c = cluster_of ? cluster_of[i] : 0;
+        const int64_t nsrc = w.off[c + 1] - w.off[c];
+        int64_t chunk = (nsrc + B - 1) / B;
+        chunk = (chunk + nt - 1) / nt * nt;
+        const int64_t used = (nsrc + chunk - 1) / chunk;
+        B = used < 1 ? 1 : (int32_t)used;
+    }
     const int64_t stride = 10 * n_act;
     constexpr int U = 16;
     double r = 0.0;
@@ -549,26 +570,37 @@ __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t 
 using KMixed = void (*)(JRecMixed, ForceWork, ForceOut, double *, int64_t, double);
 using KF64 = void (*)(JRecF64, ForceWork, ForceOut, double *, int64_t, double);
 
-template <int PREC, bool EPS0, int NW>
+template <int PREC, bool EPS0, int NW, bool PHI>
 auto pick_lpi(int lpi_log2)
 {
     using K = typename std::conditional<PREC == PREC_MIXED || PREC == PREC_PAIR32, KMixed, KF64>::type;
     static const K tab[7] = {
-        force_kernel<PREC, 1, NW, EPS0>,  force_kernel<PREC, 2, NW, EPS0>,
-        force_kernel<PREC, 4, NW, EPS0>,  force_kernel<PREC, 8, NW, EPS0>,
-        force_kernel<PREC, 16, NW, EPS0>, force_kernel<PREC, 32, NW, EPS0>,
-        force_kernel<PREC, 64, NW, EPS0>};
+        force_kernel<PREC, 1, NW, EPS0, PHI>,  force_kernel<PREC, 2, NW, EPS0, PHI>,
+        force_kernel<PREC, 4, NW, EPS0, PHI>,  force_kernel<PREC, 8, NW, EPS0, PHI>,
+        force_kernel<PREC, 16, NW, EPS0, PHI>, force_kernel<PREC, 32, NW, EPS0, PHI>,
+        force_kernel<PREC, 64, NW, EPS0, PHI>};
     return tab[lpi_log2];
 }
 
-template <int PREC, bool EPS0>
+template <int PREC, bool EPS0, bool PHI = true>
 auto pick_kernel(int lpi_log2, int nw)
 {
     if (nw == 1)
-        return pick_lpi<PREC, EPS0, 1>(lpi_log2);
+        return pick_lpi<PREC, EPS0, 1, PHI>(lpi_log2);
     if (nw == 2)
-        return pick_lpi<PREC, EPS0, 2>(lpi_log2);
-    return pick_lpi<PREC, EPS0, 4>(lpi_log2);
+        return pick_lpi<PREC, EPS0, 2, PHI>(lpi_log2);
+    return pick_lpi<PREC, EPS0, 4, PHI>(lpi_log2);
+}
+
+// the four (eps = 0, potential) variants of one precision
+template <int PREC>
+auto pick_variant(int lpi_log2, int nw, bool eps0, bool phi)
+{
+    if (eps0)
+        return phi ? pick_kernel<PREC, true, true>(lpi_log2, nw)
+                   : pick_kernel<PREC, true, false>(lpi_log2, nw);
+    return phi ? pick_kernel<PREC, false, true>(lpi_log2, nw)
+               : pick_kernel<PREC, false, false>(lpi_log2, nw);
 }
 
 int ilog2(int64_t v)
@@ -631,19 +663,15 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     const dim3 grid((unsigned)w.n_blocks, (unsigned)w.split);
     const dim3 block(64 * L.waves);
     const int prec = c.cfg.precision;
+    const bool phi = out.pot != nullptr;   // potential wanted (not in block steps)
     const int rec = prof_begin(c, PH_FORCE, n_act_total);
     if (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR) {
-        KMixed k;
-        if (prec == NBODY_PREC_MIXED)
-            k = eps0 ? pick_kernel<PREC_MIXED, true>(lg, L.waves)
-                     : pick_kernel<PREC_MIXED, false>(lg, L.waves);
-        else
-            k = eps0 ? pick_kernel<PREC_PAIR32, true>(lg, L.waves)
-                     : pick_kernel<PREC_PAIR32, false>(lg, L.waves);
+        const KMixed k = prec == NBODY_PREC_MIXED
+                             ? pick_variant<PREC_MIXED>(lg, L.waves, eps0, phi)
+                             : pick_variant<PREC_PAIR32>(lg, L.waves, eps0, phi);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jm, w, out, part, n_act_total, eps2);
     } else {
-        KF64 k = eps0 ? pick_kernel<PREC_F64, true>(lg, L.waves)
-                      : pick_kernel<PREC_F64, false>(lg, L.waves);
+        const KF64 k = pick_variant<PREC_F64>(lg, L.waves, eps0, phi);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jd, w, out, part, n_act_total, eps2);
     }
     prof_end(c, rec);
@@ -653,7 +681,8 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     const unsigned nb = (unsigned)((n_act_total * 10 + 255) / 256);
     const int rr = prof_begin(c, PH_REDUCE);
     hipLaunchKernelGGL(reduce_split, dim3(nb), dim3(256), 0, s, (const double *)c.part,
-                       w.split, n_act_total, out, 0);
+                       w.split, n_act_total, out, 0, w, (const int32_t *)c.d_cluster_of,
+                       64 * L.waves);
     prof_end(c, rr);
     return hipGetLastError();
 }
@@ -705,7 +734,8 @@ hipError_t launch_energy_pot(Ctx &c, double *phi, hipStream_t s)
     ForceOut out{};
     out.pot = phi;
     hipLaunchKernelGGL(reduce_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       (const double *)c.part, split, n, out, 1);
+                       (const double *)c.part, split, n, out, 1, ForceWork{},
+                       (const int32_t *)nullptr, 0);
     prof_end(c, rec);
     return hipGetLastError();
 }
