@@ -262,7 +262,8 @@ int64_t max_cluster(const Ctx &c)
 
 // force of the active slots described by c.d_seg (and idx) into out
 int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, const ForceOut &out,
-              double pairs_hint = -1.0, int64_t n_src = -1)
+              double pairs_hint = -1.0, int64_t n_src = -1, bool reduce = true,
+              Launch *used = nullptr, ForceWork *work = nullptr)
 {
     Launch L = pick_launch(c, n_act_typ, n_src > 0 ? n_src : max_cluster(c));
     while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
@@ -284,7 +285,11 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
         w.n_blocks = cap;
     }
     const size_t before = c.prof_pending.size();
-    HIPCHK(c, launch_force(c, w, L, out, n_act, c.stream));
+    HIPCHK(c, launch_force(c, w, L, out, n_act, c.stream, reduce));
+    if (used)
+        *used = L;
+    if (work)
+        *work = w;
     // interactions of this launch, for the profile: n_act * N with one
     // cluster; with several, the block step fills it from the schedule
     for (size_t r = before; r < c.prof_pending.size(); ++r)
@@ -373,12 +378,18 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     // launch shape from the typical active set of the clusters that have
     // one, against the largest of them
     const int64_t typ = c.nc == 1 ? n_act : std::max<int64_t>(1, n_act / std::max<int64_t>(1, tot[4]));
-    int rc = run_force(c, c.act, n_act, typ, out, (double)tot[2], tot[5]);
+    // with a split, the reduction of the partials is fused into the corrector
+    Launch L;
+    ForceWork w;
+    int rc = run_force(c, c.act, n_act, typ, out, (double)tot[2], tot[5], false, &L, &w);
     if (rc)
         return rc;
     rec = prof_begin(c, PH_CORRECT);
-    HIPCHK(c, launch_correct(c, n_act, c.act, t_target, out.vec[0], out.vec[1], out.vec[2], 1,
-                             n_act, c.stream));
+    if (w.split > 1)
+        HIPCHK(c, launch_reduce_correct(c, w, w.split, 64 * L.waves, n_act, t_target, c.stream));
+    else
+        HIPCHK(c, launch_correct(c, n_act, c.act, t_target, out.vec[0], out.vec[1], out.vec[2], 1,
+                                 n_act, c.stream));
     prof_end(c, rec);
     if (stats) {
         stats->block_steps += 1;

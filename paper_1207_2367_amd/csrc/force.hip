@@ -160,8 +160,7 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     const int64_t s0 = w.seg[c], s1 = w.seg[c + 1];
     const int64_t kb = s0 + (g - gfirst) * IB;
     const int64_t o0 = w.off[c], o1 = w.off[c + 1];
-    int64_t chunk = (o1 - o0 + w.split - 1) / w.split;
-    chunk = (chunk + NT - 1) / NT * NT;
+    const int64_t chunk = split_chunk(o1 - o0, w.split, NT);
     // splits past this cluster's sources (chunks are whole tiles, so a small
     // cluster fills fewer than B of them): nothing to do, and the reduction
     // reads only the splits in use
@@ -537,11 +536,7 @@ __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t 
     if (w.off) {
         const int64_t i = w.idx ? (int64_t)w.idx[k] : k;
         const int c = cluster_of ? cluster_of[i] : 0;
-        const int64_t nsrc = w.off[c + 1] - w.off[c];
-        int64_t chunk = (nsrc + B - 1) / B;
-        chunk = (chunk + nt - 1) / nt * nt;
-        const int64_t used = (nsrc + chunk - 1) / chunk;
-        B = used < 1 ? 1 : (int32_t)used;
+        B = (int32_t)splits_used(w.off[c + 1] - w.off[c], B, nt);
     }
     const int64_t stride = 10 * n_act;
     constexpr int U = 16;
@@ -652,7 +647,7 @@ Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
 }
 
 hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
-                        const ForceOut &out, int64_t n_act_total, hipStream_t s)
+                        const ForceOut &out, int64_t n_act_total, hipStream_t s, bool reduce)
 {
     if (n_act_total <= 0 || w.n_blocks <= 0)
         return hipSuccess;
@@ -676,7 +671,7 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     }
     prof_end(c, rec);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || w.split <= 1)
+    if (e != hipSuccess || w.split <= 1 || !reduce)
         return e;
     const unsigned nb = (unsigned)((n_act_total * 10 + 255) / 256);
     const int rr = prof_begin(c, PH_REDUCE);

@@ -412,25 +412,21 @@ __global__ void set_seg_kernel(int64_t *seg, int64_t a, int64_t b)
 // corrected velocity), end-of-step crackle/pop/5th derivative from the
 // quintic through (a, da, d2a) at both ends, Aarseth criterion with p = 6,
 // block rules.  h is the particle's own step; its block time is t + dt.
-__global__ __launch_bounds__(TPB) void correct_kernel(
-    State st, int64_t n, int64_t n_act, const int32_t *idx, double t_target,
-    const double *fa, const double *fj, const double *fs, int64_t sk, int64_t sd,
-    double eta, double dt_min, double dt_max, uint32_t *err)
+// Corrector (paper Sect. 3, item 3), interpolation of crackle, pop and the
+// fifth derivative at the end of the step, and the new block step, for
+// particle i with new a1, j1, s1 evaluated at t_i + dt_i.
+__device__ __forceinline__ void correct_one(State st, int64_t n, int64_t i, const double *a1,
+                                            const double *j1, const double *s1,
+                                            double t_target, double eta, double dt_min,
+                                            double dt_max, uint32_t *err)
 {
-    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (k >= n_act)
-        return;
-    const int64_t i = idx[k];
     const double h = st.dt[i];
     const double t_new = st.t[i] + h;
-    double a1[3], j1[3], s1[3], crk[3], pop[3], a5[3];
+    double crk[3], pop[3], a5[3];
     uint32_t bad = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int64_t e = (int64_t)d * n + i;
-        a1[d] = fa[k * sk + d * sd];
-        j1[d] = fj[k * sk + d * sd];
-        s1[d] = fs[k * sk + d * sd];
         const double a0 = st.acc[e], j0 = st.jrk[e], s0 = st.snp[e];
         const double v0 = st.vel[e], r0 = st.pos[e];
         const double v1 = v0 + h * 0.5 * (a1[d] + a0) - h * h * 0.1 * (j1[d] - j0) +
@@ -470,6 +466,71 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
         st.dt[i] = dtn;
     if (bad)
         atomicOr(err, bad);
+}
+
+__global__ __launch_bounds__(TPB) void correct_kernel(
+    State st, int64_t n, int64_t n_act, const int32_t *idx, double t_target,
+    const double *fa, const double *fj, const double *fs, int64_t sk, int64_t sd,
+    double eta, double dt_min, double dt_max, uint32_t *err)
+{
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= n_act)
+        return;
+    double a1[3], j1[3], s1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a1[d] = fa[k * sk + d * sd];
+        j1[d] = fj[k * sk + d * sd];
+        s1[d] = fs[k * sk + d * sd];
+    }
+    correct_one(st, n, idx[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+}
+
+// Split-source reduction and corrector of a block step in one kernel: a
+// workgroup takes RC_SLOTS active slots; thread (q, slot) sums quantity q
+// (a, da, d2a components) over the splits that hold the slot's cluster, in
+// the fixed order b = 0 .. B_c - 1 with 16 loads in flight, into LDS; then
+// one thread per slot runs the corrector on the sums.  part is the
+// evaluation's [B][10][n_act] buffer (the potential slot is not used).
+constexpr int RC_SLOTS = TPB / 9;
+__global__ __launch_bounds__(TPB) void reduce_correct_kernel(
+    State st, int64_t n, int64_t n_act, const double *part, int32_t B, int nt, ForceWork w,
+    const int32_t *cluster_of, double t_target, double eta, double dt_min, double dt_max,
+    uint32_t *err)
+{
+    __shared__ double sum[9][RC_SLOTS];
+    const int q = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
+    const int64_t k0 = (int64_t)blockIdx.x * RC_SLOTS;
+    const int64_t k = k0 + kl;
+    if (q < 9 && k < n_act) {
+        const int64_t i = w.idx[k];
+        const int c = cluster_of ? cluster_of[i] : 0;
+        const int64_t bc = splits_used(w.off[c + 1] - w.off[c], B, nt);
+        const double *p = part + (int64_t)q * n_act + k;
+        const int64_t stride = 10 * n_act;
+        constexpr int U = 16;
+        double r = 0.0;
+        int64_t b = 0;
+        for (; b + U <= bc; b += U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = p[(b + u) * stride];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                r += v[u];
+        }
+        for (; b < bc; ++b)
+            r += p[b * stride];
+        sum[q][kl] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < RC_SLOTS && k < n_act) {
+        const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
+        const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
+        const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
+        correct_one(st, n, w.idx[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+    }
 }
 
 // first step after the start-up evaluation: the generalized criterion at
@@ -700,6 +761,19 @@ hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx, doubl
         return hipSuccess;
     hipLaunchKernelGGL(correct_kernel, dim3(nblk(n_act)), dim3(TPB), 0, s, c.st, c.n, n_act,
                        idx, t_target, fa, fj, fs, sk, sd, c.cfg.eta, c.cfg.dt_min,
+                       c.cfg.dt_max, c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, int nt,
+                                 int64_t n_act, double t_target, hipStream_t s)
+{
+    if (n_act <= 0)
+        return hipSuccess;
+    const unsigned nb = (unsigned)((n_act + RC_SLOTS - 1) / RC_SLOTS);
+    hipLaunchKernelGGL(reduce_correct_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.n, n_act,
+                       (const double *)c.part, (int32_t)split, nt, w,
+                       (const int32_t *)c.d_cluster_of, t_target, c.cfg.eta, c.cfg.dt_min,
                        c.cfg.dt_max, c.d_err);
     return hipGetLastError();
 }

@@ -64,11 +64,29 @@ struct Launch {
     int lpi = 0, waves = 0, split = 0;
 };
 
+// Sources per split of a cluster of nsrc sources under split factor B with
+// tiles of nt: ceil(nsrc / B) rounded up to whole tiles; the splits in use
+// are those that start below nsrc (at least one).
+__host__ __device__ inline int64_t split_chunk(int64_t nsrc, int64_t B, int64_t nt)
+{
+    const int64_t c = (nsrc + B - 1) / B;
+    return (c + nt - 1) / nt * nt;
+}
+__host__ __device__ inline int64_t splits_used(int64_t nsrc, int64_t B, int64_t nt)
+{
+    const int64_t c = split_chunk(nsrc, B, nt);
+    const int64_t u = c > 0 ? (nsrc + c - 1) / c : 1;
+    return u < 1 ? 1 : u;
+}
+
 struct Ctx;
 
 // force.hip
 hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
-                        const ForceOut &out, int64_t n_act_total, hipStream_t s);
+                        const ForceOut &out, int64_t n_act_total, hipStream_t s,
+                        bool reduce = true);
+hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, int nt,
+                                 int64_t n_act, double t_target, hipStream_t s);
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
 // start-up evaluation (FP64, a, da, d2a and crackle of every particle from
 // the stored state): split = 1, results written straight to out
