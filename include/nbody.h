@@ -228,7 +228,8 @@ int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape);
 /* GPU time per phase of the block step, measured with HIP events on the
    context's stream while profiling is on (phases follow the paper's
    Table 1: 0 active-set selection, 1 prediction, 2 evaluation (force
-   kernel), 3 split-source reduction, 4 correction and new steps, 5 energy).
+   kernel), 3 split-source reduction (of nbody_force; a block step fuses
+   it into 4), 4 correction and new steps, 5 energy).
    nbody_profile(ctx, enable, out): enable = 1 starts (and clears), 0 stops;
    with out != NULL the totals so far are written (synchronizes).  The
    force-kernel launches are also logged one by one: nbody_profile_force_log

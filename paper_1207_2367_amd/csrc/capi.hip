@@ -268,6 +268,13 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     Launch L = pick_launch(c, n_act_typ, n_src > 0 ? n_src : max_cluster(c));
     while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
         L.split >>= 1;
+    // a batched launch gets its parallelism from its many clusters: the
+    // shape chosen for one cluster's active set would split every cluster's
+    // sources as finely, so cap the whole grid at 2^20 lanes (the size the
+    // autotuner picks for one large block) by halving the split
+    if (c.nc > 1 && c.pinned.lpi == 0)
+        while (L.split > 1 && n_act * L.lpi * L.split > (int64_t(1) << 20))
+            L.split >>= 1;
     const int64_t ib = iblock_size(L);
     ForceWork w{};
     w.idx = idx;
@@ -824,7 +831,7 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
     int rc = NBODY_OK;
     std::vector<int32_t> hidx;
     // sizes whose single launch stays below ~2^35 pairs (tens of ms); larger
-    // active sets keep the heuristic shape, which is then saturating anyway
+    // active sets keep the launch rule, which is then saturating anyway
     for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc &&
                     (int64_t(1) << b) * nsrc <= (int64_t(1) << 35); ++b) {
         const int64_t na = int64_t(1) << b;
