@@ -174,8 +174,14 @@ def cpu_baseline(n, seconds):
         el += e
         pairs += float(na) * n
         reps += 1
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(pairs / el / 1e9, 4), "unit": "G interactions/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model,
             "sample": f"{reps} block step(s) of the N={n} Plummer sphere, each with a random active "
                       f"set of {na} particles (predict all N, evaluate {na} x {n} pairs, correct): "
                       f"{el:.1f} s in total, FP64 C oracle, OpenMP over active particles"}

@@ -28,9 +28,13 @@
 //     accuracy by one third-order step;
 //   - the potential energy (energy_kernel) takes every pair once, with a
 //     cyclic half-window per particle that gives every workgroup equal work;
-//   - grid.y = B splits the sources; partial results go to a [B][10][n_act]
-//     buffer that a second kernel sums in fixed order b = 0 .. B-1, so the
-//     result does not depend on scheduling (no float atomics anywhere).
+//   - grid.y = B splits the sources (chunks of whole tiles; a cluster with
+//     fewer tiles uses fewer splits, the rest exit at once); partial results
+//     go to a [B][10][n_act] buffer that a second kernel sums in fixed order
+//     b = 0 .. B_c-1 (reduce_split here, or the corrector's kernel in a block
+//     step), so the result does not depend on scheduling (no float atomics
+//     anywhere);
+//   - a block step's evaluation skips the potential (template flag PHI).
 #include "nbody_internal.h"
 
 namespace nb {
