@@ -252,6 +252,17 @@ hipError_t nb::prof_collect(Ctx &c)
 
 namespace {
 
+// the autotuner has a shape for this active-set size
+bool has_tuned(const Ctx &c, int64_t n_act)
+{
+    if (n_act < 1 || c.tuned.empty())
+        return false;
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n_act)
+        ++b;
+    return b < (int)c.tuned.size() && c.tuned[b].lpi > 0;
+}
+
 int64_t max_cluster(const Ctx &c)
 {
     int64_t m = 0;
@@ -268,11 +279,12 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     Launch L = pick_launch(c, n_act_typ, n_src > 0 ? n_src : max_cluster(c));
     while ((int64_t)L.split * n_act > c.part_cap && L.split > 1)
         L.split >>= 1;
-    // a batched launch gets its parallelism from its many clusters: the
-    // shape chosen for one cluster's active set would split every cluster's
-    // sources as finely, so cap the whole grid at 2^20 lanes (the size the
-    // autotuner picks for one large block) by halving the split
-    if (c.nc > 1 && c.pinned.lpi == 0)
+    // a batched launch gets its parallelism from its many clusters: the rule's
+    // shape for one cluster's active set would split every cluster's sources
+    // as finely, so cap the whole grid at 2^20 lanes (the size the autotuner
+    // picks for one large block) by halving the split.  Autotuned shapes of a
+    // batched context were measured on batched blocks and are kept.
+    if (c.nc > 1 && c.pinned.lpi == 0 && !has_tuned(c, n_act_typ))
         while (L.split > 1 && n_act * L.lpi * L.split > (int64_t(1) << 20))
             L.split >>= 1;
     const int64_t ib = iblock_size(L);
@@ -830,45 +842,52 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
     std::vector<Launch> table;
     int rc = NBODY_OK;
     std::vector<int32_t> hidx;
-    // sizes whose single launch stays below ~2^35 pairs (tens of ms); larger
-    // active sets keep the launch rule, which is then saturating anyway
-    for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc &&
-                    (int64_t(1) << b) * nsrc <= (int64_t(1) << 35); ++b) {
+    // per size na (a power of two): one system takes na evenly spread
+    // particles; a batched context takes up to na particles of every cluster,
+    // the block a batched step with typical active set na looks like.  Sizes
+    // whose single launch stays below ~2^35 pairs (tens of ms); larger active
+    // sets keep the launch rule, which is then saturating anyway.
+    for (int b = 0; rc == NBODY_OK && (int64_t(1) << b) <= nsrc; ++b) {
         const int64_t na = int64_t(1) << b;
-        // evenly spread active particles of the largest cluster
-        hidx.resize(na);
-        for (int64_t k = 0; k < na; ++k)
-            hidx[k] = (int32_t)(c.off[big] + k * nsrc / na);
-        if (hipMemcpyAsync(c.act, hidx.data(), na * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hidx.clear();
+        double pairs = 0.0;
+        for (size_t q = (c.nc > 1 ? 0 : big); q + 1 < c.off.size(); ++q) {
+            const int64_t size = c.off[q + 1] - c.off[q];
+            const int64_t cnt = std::min(na, size);
+            for (int64_t k = 0; k < cnt; ++k)
+                hidx.push_back((int32_t)(c.off[q] + k * size / cnt));
+            pairs += (double)cnt * (double)size;
+            if (c.nc == 1)
+                break;
+        }
+        if (pairs > std::ldexp(1.0, 35))
+            break;
+        const int64_t nt = (int64_t)hidx.size();
+        if (hipMemcpyAsync(c.act, hidx.data(), nt * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = hip_fail(c, hipGetLastError(), "autotune copy");
             break;
         }
-        if (c.nc > 1) {
-            if (launch_segments(c, c.act, na, s) != hipSuccess) {
-                rc = hip_fail(c, hipGetLastError(), "autotune segments");
-                break;
-            }
-        } else if (launch_segments(c, c.act, na, s) != hipSuccess) {
+        if (launch_segments(c, c.act, nt, s) != hipSuccess) {
             rc = hip_fail(c, hipGetLastError(), "autotune segments");
             break;
         }
         ForceOut out{};
         out.vec[0] = c.fnew;
-        out.vec[1] = c.fnew + 3 * na;
-        out.vec[2] = c.fnew + 6 * na;
+        out.vec[1] = c.fnew + 3 * nt;
+        out.vec[2] = c.fnew + 6 * nt;
         out.sk = 1;
-        out.sd = na;
+        out.sd = nt;
         Launch best{};
         float best_ms = 1e30f;
         double spent = 0.0;
         for (int waves : {4, 2, 1}) {
             for (int lpi = 1; lpi <= 64; lpi <<= 1) {
                 for (int split = 1; split <= 4096; split <<= 1) {
-                    const int64_t lanes = na * lpi * split;
+                    const int64_t lanes = nt * lpi * split;
                     if (lanes < (int64_t(1) << 14) && !(lpi == 64 && split >= nsrc / (64 * waves)))
                         continue;   // too little parallelism (unless nothing more is possible)
-                    if (lanes > (int64_t(1) << 22) || split * na > c.part_cap)
+                    if (lanes > (int64_t(1) << 22) || split * nt > c.part_cap)
                         continue;
                     if (split > 1 && nsrc / split < 64 * waves)
                         continue;   // less than one tile per split
@@ -884,7 +903,7 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
                     bool ok = true;
                     for (int rep = 0, reps = 3; rep < reps && ok; ++rep) {
                         ok = hipEventRecord(e0, s) == hipSuccess;
-                        ok = ok && run_force(c, c.act, na, na, out) == NBODY_OK;
+                        ok = ok && run_force(c, c.act, nt, na, out) == NBODY_OK;
                         ok = ok && hipEventRecord(e1, s) == hipSuccess;
                         ok = ok && hipEventSynchronize(e1) == hipSuccess;
                         float t = 0.0f;
