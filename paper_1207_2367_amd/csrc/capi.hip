@@ -284,9 +284,18 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     // as finely, so cap the whole grid at 2^20 lanes (the size the autotuner
     // picks for one large block) by halving the split.  Autotuned shapes of a
     // batched context were measured on batched blocks and are kept.
-    if (c.nc > 1 && c.pinned.lpi == 0 && !has_tuned(c, n_act_typ))
-        while (L.split > 1 && n_act * L.lpi * L.split > (int64_t(1) << 20))
-            L.split >>= 1;
+    if (c.nc > 1 && c.pinned.lpi == 0) {
+        if (!has_tuned(c, n_act_typ))
+            while (L.split > 1 && n_act * L.lpi * L.split > (int64_t(1) << 20))
+                L.split >>= 1;
+        // a batched block with few active clusters: at least 2^16 lanes,
+        // splitting further while every split keeps a tile of the largest
+        const int64_t ns = n_src > 0 ? n_src : max_cluster(c);
+        while (n_act * L.lpi * L.split < (int64_t(1) << 16) &&
+               ns / ((int64_t)L.split * 2) >= 64 * L.waves &&
+               (int64_t)L.split * 2 * n_act <= c.part_cap)
+            L.split <<= 1;
+    }
     const int64_t ib = iblock_size(L);
     ForceWork w{};
     w.idx = idx;
