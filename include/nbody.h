@@ -203,10 +203,11 @@ int nbody_set_state(nbody_ctx *ctx, const double *d_pos, const double *d_vel,
 int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3]);
 
 /* Measure launch shapes of the force kernel for active-set sizes
-   1, 2, 4, ... up to the largest cluster, with active particles spread
-   over the largest cluster (sizes whose single launch would exceed ~2^35
-   pairs keep the launch rule), and keep the fastest for each size range
-   in the context (the autotuner).  Without it a fixed rule picks the
+   1, 2, 4, ... up to the largest cluster -- with one system, that many
+   particles spread over it; with clusters, up to that many particles of
+   every cluster, as in a batched block step -- (sizes whose single launch
+   would exceed ~2^35 pairs keep the launch rule), and keep the fastest for
+   each size range in the context (the autotuner).  Without it a fixed rule picks the
    shape.  max_ms bounds the time spent per size.  Uses the stored state
    as sources; does not change it.  Synchronizes.  Errors: EDEVICE.      */
 int nbody_autotune(nbody_ctx *ctx, double max_ms);
