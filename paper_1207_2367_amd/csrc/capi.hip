@@ -379,10 +379,9 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     int rec = prof_begin(c, PH_SCHED);
     HIPCHK(c, launch_sched_head(c, t_target, c.stream));   // totals also into h_tot
     HIPCHK(c, hipEventRecord(c.ev_info, c.stream));
-    HIPCHK(c, launch_sched_scatter(c, c.stream));
     prof_end(c, rec);
-    rec = prof_begin(c, PH_PREDICT);
-    HIPCHK(c, launch_pack(c, c.d_tblock, 0, c.d_cluster_of, c.stream));
+    rec = prof_begin(c, PH_PREDICT);   // the compaction of the active list runs here too
+    HIPCHK(c, launch_scatter_pack(c, c.stream));
     prof_end(c, rec);
     HIPCHK(c, hipEventSynchronize(c.ev_info));
     int64_t tot[8];

@@ -67,11 +67,11 @@ __device__ uint32_t block_dt(double crit, double dt_old, double t_new, double t_
 // Taylor series of paper Sect. 3 item 1 (Horner form) to the source
 // records.  T is the block time of the particle's cluster, or its own time
 // (h = 0: the records are the stored state) when own_time is set.
-__global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF64 jd,
-                                                   int prec, int64_t n, const double *Tc,
-                                                   const int32_t *cluster_of, int own_time)
+__device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
+                                         const JRecF64 &jd, int prec, int64_t n,
+                                         const double *Tc, const int32_t *cluster_of,
+                                         int own_time, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n)
         return;
     const double ti = st.t[i];
@@ -104,6 +104,14 @@ __global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF
         jd.ax[i] = ap[0]; jd.ay[i] = ap[1]; jd.az[i] = ap[2];
         jd.m[i] = m;
     }
+}
+
+__global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF64 jd,
+                                                   int prec, int64_t n, const double *Tc,
+                                                   const int32_t *cluster_of, int own_time)
+{
+    pack_one(st, jm, jd, prec, n, Tc, cluster_of, own_time,
+             (int64_t)blockIdx.x * TPB + threadIdx.x);
 }
 
 // Predictor to FP64 [n][3] outputs at a common time t (diagnostic entry).
@@ -157,39 +165,6 @@ __device__ __forceinline__ void min_count(uint64_t &v, int &n, uint64_t ov, int 
     }
 }
 
-__global__ __launch_bounds__(TPB) void sched_min(const double *t, const double *dt,
-                                                 const int64_t *chunk_begin,
-                                                 const int32_t *chunk_cluster, uint64_t *tmin,
-                                                 uint64_t *cmin, int32_t *ccnt)
-{
-    __shared__ uint64_t rv[TPB / 64];
-    __shared__ int rn[TPB / 64];
-    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
-    uint64_t v = ~0ull;
-    int n = 0;
-    for (int64_t i = b + threadIdx.x; i < e; i += TPB)
-        min_count(v, n, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
-    // xor butterfly: both partners form the same (min, count) of their union
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t ov = __shfl_xor(v, m, 64);
-        const int on = __shfl_xor(n, m, 64);
-        min_count(v, n, ov, on);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        rv[threadIdx.x >> 6] = v;
-        rn[threadIdx.x >> 6] = n;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < TPB / 64; ++w)
-            min_count(v, n, rv[w], rn[w]);
-        cmin[blockIdx.x] = v;
-        ccnt[blockIdx.x] = n;
-        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)v);
-    }
-}
-
 __device__ __forceinline__ bool due(double t, double dt, double T) { return t + dt == T; }
 
 // Single workgroup: the due count of every chunk (its count at its minimum
@@ -200,15 +175,12 @@ __device__ __forceinline__ bool due(double t, double dt, double T) { return t + 
 // info[0] = N_act total, info[1] = bits of the earliest block time,
 // info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot,
 // info[4] = clusters with active particles, info[5] = the largest of them.
-__global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
-                                                   int64_t n_chunks,
-                                                   const int32_t *chunk_cluster,
-                                                   uint64_t *tmin, const int64_t *off,
-                                                   int32_t nc, double t_target,
-                                                   int64_t *chunk_pos, int64_t *seg,
-                                                   double *tblock, int64_t *info,
-                                                   int64_t *hist, const uint32_t *err,
-                                                   int64_t *info_host)
+__device__ __forceinline__ void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
+                                           int64_t n_chunks, const int32_t *chunk_cluster,
+                                           uint64_t *tmin, const int64_t *off, int32_t nc,
+                                           double t_target, int64_t *chunk_pos, int64_t *seg,
+                                           double *tblock, int64_t *info, int64_t *hist,
+                                           const uint32_t *err, int64_t *info_host)
 {
     __shared__ int64_t buf[1024];
     __shared__ int64_t carry;
@@ -318,19 +290,74 @@ __global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const i
     }
 }
 
+// The schedule's head, one workgroup of 1024 lanes per chunk: the chunk's
+// minimum of t + dt (as ordered bits; times are >= 0 so the IEEE bits order
+// like the values) and how many of its particles reach it, into cmin/ccnt
+// and the cluster's slot of tmin (a chunk's particles are due exactly when
+// its minimum is the cluster's block time).  The last workgroup to finish
+// (arrival counter, with device-scope fences on both sides so that it sees
+// every other workgroup's results) then runs the scan above and leaves the
+// counter at zero for the next schedule.
+__global__ __launch_bounds__(1024) void sched_head_kernel(
+    const double *t, const double *dt, const int64_t *chunk_begin,
+    const int32_t *chunk_cluster, uint64_t *tmin, uint64_t *cmin, int32_t *ccnt,
+    unsigned long long *arrive, int64_t n_chunks, const int64_t *off, int32_t nc,
+    double t_target, int64_t *chunk_pos, int64_t *seg, double *tblock, int64_t *info,
+    int64_t *hist, const uint32_t *err, int64_t *info_host)
+{
+    constexpr int NT = 1024;
+    __shared__ uint64_t rv[NT / 64];
+    __shared__ int rn[NT / 64];
+    __shared__ int last;
+    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
+    uint64_t v = ~0ull;
+    int n = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += NT)
+        min_count(v, n, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
+    // xor butterfly: both partners form the same (min, count) of their union
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t ov = __shfl_xor(v, m, 64);
+        const int on = __shfl_xor(n, m, 64);
+        min_count(v, n, ov, on);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rv[threadIdx.x >> 6] = v;
+        rn[threadIdx.x >> 6] = n;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NT / 64; ++w)
+            min_count(v, n, rv[w], rn[w]);
+        cmin[blockIdx.x] = v;
+        ccnt[blockIdx.x] = n;
+        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)v);
+        __threadfence();   // this chunk's results before the arrival
+        last = atomicAdd(arrive, 1ull) == (unsigned long long)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();       // every other chunk's results after the arrivals
+    if (threadIdx.x == 0)
+        *arrive = 0ull;
+    sched_scan(cmin, ccnt, n_chunks, chunk_cluster, tmin, off, nc, t_target, chunk_pos, seg,
+               tblock, info, hist, err, info_host);
+}
+
 // ordered compaction of the due particles of each chunk
-__global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const double *dt,
-                                                     const int64_t *chunk_begin,
-                                                     const int32_t *chunk_cluster,
-                                                     const double *tblock,
-                                                     const int64_t *chunk_pos, int32_t *act)
+__device__ __forceinline__ void scatter_chunk(const double *t, const double *dt,
+                                              const int64_t *chunk_begin,
+                                              const int32_t *chunk_cluster,
+                                              const double *tblock, const int64_t *chunk_pos,
+                                              int32_t *act, int64_t q)
 {
     __shared__ int wsum[TPB / 64];
-    const double T = tblock[chunk_cluster[blockIdx.x]];
+    const double T = tblock[chunk_cluster[q]];
     if (!(T < DBL_MAX))
         return;
-    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
-    int64_t pos = chunk_pos[blockIdx.x];
+    const int64_t b = chunk_begin[q], e = chunk_begin[q + 1];
+    int64_t pos = chunk_pos[q];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t base = b; base < e; base += TPB) {
         const int64_t i = base + threadIdx.x;
@@ -352,29 +379,99 @@ __global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const doub
     }
 }
 
+__global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const double *dt,
+                                                     const int64_t *chunk_begin,
+                                                     const int32_t *chunk_cluster,
+                                                     const double *tblock,
+                                                     const int64_t *chunk_pos, int32_t *act)
+{
+    scatter_chunk(t, dt, chunk_begin, chunk_cluster, tblock, chunk_pos, act, blockIdx.x);
+}
+
+// A block step's compaction and predictor in one launch: the first n_chunks
+// workgroups compact one chunk each, the rest predict TPB sources each to
+// their cluster's block time.  Both read only the schedule's results and
+// the stored state; they write disjoint arrays.
+__global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed jm, JRecF64 jd,
+                                                           int prec, int64_t n,
+                                                           const int32_t *cluster_of,
+                                                           const int64_t *chunk_begin,
+                                                           const int32_t *chunk_cluster,
+                                                           const double *tblock,
+                                                           const int64_t *chunk_pos,
+                                                           int32_t *act, int64_t n_chunks)
+{
+    if ((int64_t)blockIdx.x < n_chunks)
+        scatter_chunk(st.t, st.dt, chunk_begin, chunk_cluster, tblock, chunk_pos, act,
+                      blockIdx.x);
+    else
+        pack_one(st, jm, jd, prec, n, tblock, cluster_of, 0,
+                 ((int64_t)blockIdx.x - n_chunks) * TPB + threadIdx.x);
+}
+
 // i-block tables of a force launch over clusters: cluster c gets
-// ceil(n_c / ib) blocks starting at blk_first[c]; the rest of the grid
-// (up to cap) is marked -1 (idle).
+// ceil(n_c / ib) blocks starting at blk_first[c] (an exclusive scan over the
+// clusters, 1024 at a time, as in the schedule's scan); every grid slot g
+// below the total then finds its cluster by a binary search over the starts
+// (kept in LDS for up to BLK_LDS clusters), the rest of the grid (up to cap)
+// is marked -1 (idle).  All of it in parallel: no loop over the clusters or
+// over one cluster's blocks runs on a single lane.
+constexpr int BLK_LDS = 8192;
 __global__ __launch_bounds__(1024) void blocks_kernel(const int64_t *seg, int32_t nc, int64_t ib,
                                                       int64_t cap, int64_t *blk_first,
                                                       int32_t *blk_cluster)
 {
-    __shared__ int64_t total;
-    if (threadIdx.x == 0) {
-        int64_t g = 0;
-        for (int32_t c = 0; c < nc; ++c) {
-            blk_first[c] = g;
-            g += (seg[c + 1] - seg[c] + ib - 1) / ib;
-        }
-        blk_first[nc] = g;
-        total = g;
-    }
+    __shared__ int64_t buf[1024];
+    __shared__ int32_t first[BLK_LDS];
+    __shared__ int64_t carry;
+    const bool in_lds = nc <= BLK_LDS;
+    if (threadIdx.x == 0)
+        carry = 0;
     __syncthreads();
-    for (int32_t c = threadIdx.x; c < nc; c += 1024)
-        for (int64_t g = blk_first[c]; g < blk_first[c + 1]; ++g)
-            blk_cluster[g] = c;
-    for (int64_t g = total + threadIdx.x; g < cap; g += 1024)
-        blk_cluster[g] = -1;
+    for (int32_t base = 0; base < nc; base += 1024) {
+        const int32_t c = base + (int32_t)threadIdx.x;
+        const int64_t v = c < nc ? (seg[c + 1] - seg[c] + ib - 1) / ib : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 1024; s <<= 1) {
+            const int64_t add = threadIdx.x >= (unsigned)s ? buf[threadIdx.x - s] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (c < nc) {
+            const int64_t f = carry + buf[threadIdx.x] - v;
+            blk_first[c] = f;
+            if (in_lds)
+                first[c] = (int32_t)f;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023)
+            carry += buf[1023];
+        __syncthreads();
+    }
+    const int64_t total = carry;
+    if (threadIdx.x == 0)
+        blk_first[nc] = total;
+    __syncthreads();
+    for (int64_t g = threadIdx.x; g < cap; g += 1024) {
+        int32_t cl = -1;
+        if (g < total) {
+            // the last cluster that starts at or before g (a cluster without
+            // blocks starts where the next one does, so the last is the owner)
+            int32_t lo = 0, hi = nc - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                const int64_t fm = in_lds ? (int64_t)first[mid] : blk_first[mid];
+                if (fm <= g)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            cl = lo;
+        }
+        blk_cluster[g] = cl;
+    }
 }
 
 // active segments of a caller's ascending index list: seg[c] = first slot
@@ -706,16 +803,26 @@ hipError_t launch_sched_reset(const Ctx &c, hipStream_t s)
 // per-cluster minima must be reset (at init, and by every scan after use)
 hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s)
 {
-    hipLaunchKernelGGL(sched_min, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
+    hipLaunchKernelGGL(sched_head_kernel, dim3((unsigned)c.n_chunks), dim3(1024), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
-                       c.d_tmin, c.d_chunk_min, c.d_chunk_cnt);
-    hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const uint64_t *)c.d_chunk_min,
-                       (const int32_t *)c.d_chunk_cnt, c.n_chunks,
-                       (const int32_t *)c.d_chunk_cluster,
-                       c.d_tmin, (const int64_t *)c.d_off, c.nc, t_target,
-                       c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info, c.d_info + 8,
-                       (const uint32_t *)c.d_err, c.d_tot);
+                       c.d_tmin, c.d_chunk_min, c.d_chunk_cnt,
+                       reinterpret_cast<unsigned long long *>(c.d_info + INFO_ARRIVE),
+                       c.n_chunks, (const int64_t *)c.d_off, c.nc, t_target, c.d_chunk_pos,
+                       c.d_seg, c.d_tblock, c.d_info, c.d_info + 8, (const uint32_t *)c.d_err,
+                       c.d_tot);
+    return hipGetLastError();
+}
+
+// compaction of the active list and predictor of a block step, one launch
+hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s)
+{
+    const unsigned nb = (unsigned)c.n_chunks + nblk(c.n);
+    hipLaunchKernelGGL(scatter_pack_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.jm, c.jd,
+                       (int)c.cfg.precision, c.n, (const int32_t *)c.d_cluster_of,
+                       (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
+                       (const double *)c.d_tblock, (const int64_t *)c.d_chunk_pos, c.act,
+                       c.n_chunks);
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s);
 hipError_t launch_sched_reset(const Ctx &c, hipStream_t s);
 hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s);
 hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s);
+hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s);
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
 hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
@@ -127,6 +128,9 @@ enum : uint32_t { ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u };
 // Schedule scratch: chunk table built at init (a chunk never spans two
 // clusters), per-cluster block times and active segments.
 constexpr int SCHED_CHUNK = 2048;
+// slot of the device info array that holds the schedule's arrival counter
+// (zero between schedules)
+constexpr int INFO_ARRIVE = 56;
 
 // Event-based timing of the phases of a block step (host side).
 enum Phase { PH_SCHED = 0, PH_PREDICT, PH_FORCE, PH_REDUCE, PH_CORRECT, PH_ENERGY, PH_N };
@@ -169,7 +173,8 @@ struct Ctx {
     int64_t *d_seg = nullptr;            // [nc + 1] active segments
     int32_t *d_blk_cluster = nullptr;    // [n / 1 + nc] i-block -> cluster
     int64_t *d_blk_first = nullptr;      // [nc + 1]
-    int64_t *d_info = nullptr;           // [64]: [0..7] step info, [8..47] N_act histogram
+    int64_t *d_info = nullptr;           // [64]: [0..7] step info, [8..47] N_act histogram,
+                                         // [INFO_ARRIVE] the schedule's arrival counter
     uint32_t *d_err = nullptr;           // device error word
     double *d_red = nullptr;             // reduction scratch
     int64_t red_cap = 0;

@@ -136,6 +136,34 @@ def test_force_clusters(prec):
         _check(prec, force(s, idx), ref, kap)
 
 
+def test_force_many_clusters():
+    """1500 clusters of 1-12 bodies (more clusters than the 1024 lanes of
+    the block-table scan), a third of them without active particles: each
+    active particle feels only its own cluster, in a split and an unsplit
+    shape."""
+    rng = np.random.default_rng(1500)
+    sizes = rng.integers(1, 13, 1500)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    m, x, v, a = plummer_inputs(int(off[-1]), 1501)
+    keep = rng.random(sizes.size) < 2 / 3
+    idx = np.sort(np.concatenate([np.arange(off[c], off[c + 1])[rng.random(sizes[c]) < 0.5]
+                                  for c in range(sizes.size) if keep[c]]))
+    log_case(test="many_clusters", n=m.size, clusters=sizes.size, n_act=idx.size)
+    ref = [np.zeros((idx.size, 3)) for _ in range(3)] + [np.zeros(idx.size)]
+    kap = np.zeros((idx.size, 4))
+    cl = np.searchsorted(off, idx, side="right") - 1
+    for c in np.unique(cl):
+        sel = cl == c
+        r = oracle.force(m, x, v, a, EPS, idx[sel], (off[c], off[c + 1]))
+        kap[sel] = kappa(m, x, v, a, EPS, idx[sel], (off[c], off[c + 1]))
+        for q in range(4):
+            ref[q][sel] = r[q]
+    s = gpu_system(m, x, v, a, EPS, 0, offsets=off)
+    for shape in ((0, 0, 0), (1, 4, 1), (16, 1, 2)):
+        s.set_launch(*shape)
+        _check(0, force(s, idx), ref, kap)
+
+
 def test_force_validate_rejects_bad_index():
     from paper_1207_2367_amd import NBodyError
     m, x, v, a = plummer_inputs(512, 1)

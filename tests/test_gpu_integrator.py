@@ -88,11 +88,18 @@ def test_predict_parity():
 
 
 # ------------------------------------------------------------ scheduler
-@pytest.mark.parametrize("clusters", [False, True])
+@pytest.mark.parametrize("clusters", [0, 4, 1300], ids=["one", "four", "many"])
 def test_schedule_parity(clusters):
+    """Active set and block time against the oracle's schedule, per cluster;
+    1300 clusters give more schedule chunks than the scan's 1024 lanes."""
     n = 9001
     m, x, v, a, jk, sn, cr, t, dt = _random_state(n, 9)
-    off = [0, 2500, 2501, 7000, n] if clusters else None
+    off = None
+    if clusters == 4:
+        off = [0, 2500, 2501, 7000, n]
+    elif clusters:
+        cuts = np.sort(np.random.default_rng(1300).choice(np.arange(1, n), clusters - 1, replace=False))
+        off = [0] + [int(q) for q in cuts] + [n]
     s = _system(m, x, v, 0, offsets=off)
     s.set_state(t=t, dt=dt)
     for T in (1.0, 0.0625, 2.0 ** -9):
