@@ -368,24 +368,52 @@ int run_force_init(Ctx &c)
     return NBODY_OK;
 }
 
+// Waits until the schedule launched with sequence number seq has put its
+// totals into the mapped host words, by polling the sequence word (the
+// kernel stores it after the totals with system-scope release order); every
+// 1024 polls the stream is queried, so that a failed or finished stream
+// that never wrote the word ends the wait with an error instead of a hang.
+int wait_totals(Ctx &c, int64_t seq, int64_t tot[6])
+{
+    for (uint32_t spin = 1;; ++spin) {
+        if (__atomic_load_n(&c.h_tot[6], __ATOMIC_ACQUIRE) == seq)
+            break;
+        if ((spin & 1023u) == 0) {
+            const hipError_t e = hipStreamQuery(c.stream);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&c.h_tot[6], __ATOMIC_ACQUIRE) == seq)
+                    break;
+                return fail(c, NBODY_EDEVICE, "the schedule did not report its totals");
+            }
+            if (e != hipErrorNotReady)
+                return hip_fail(c, e, "schedule");
+        }
+        __builtin_ia32_pause();
+    }
+    for (int q = 0; q < 6; ++q)
+        tot[q] = __atomic_load_n(&c.h_tot[q], __ATOMIC_RELAXED);
+    return NBODY_OK;
+}
+
 // one block step; fills n_act / t_block and adds to stats
 int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
                nbody_step_stats *stats)
 {
     // the host needs N_act (and the block time) to size the evaluation; it
-    // waits for the copy of the scan's totals only, while the GPU goes on
-    // with the compaction of the active list and the predictor (which skips
-    // clusters past the target, so it is harmless when nothing is due)
+    // waits for the scan's totals only (written into mapped host memory),
+    // while the GPU goes on with the compaction of the active list and the
+    // predictor (which skips clusters past the target, so it is harmless
+    // when nothing is due)
     int rec = prof_begin(c, PH_SCHED);
-    HIPCHK(c, launch_sched_head(c, t_target, c.stream));   // totals also into h_tot
-    HIPCHK(c, hipEventRecord(c.ev_info, c.stream));
+    const int64_t seq = ++c.sched_seq;
+    HIPCHK(c, launch_sched_head(c, t_target, seq, c.stream));
     prof_end(c, rec);
     rec = prof_begin(c, PH_PREDICT);   // the compaction of the active list runs here too
     HIPCHK(c, launch_scatter_pack(c, c.stream));
     prof_end(c, rec);
-    HIPCHK(c, hipEventSynchronize(c.ev_info));
-    int64_t tot[8];
-    std::memcpy(tot, c.h_tot, sizeof tot);
+    int64_t tot[6];
+    if (int rc = wait_totals(c, seq, tot))
+        return rc;
     const int64_t n_act = tot[0];
     double tb;
     std::memcpy(&tb, &tot[1], 8);
@@ -504,8 +532,6 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
     auto bail = [&](int rc) {
         if (c.h_tot)
             (void)hipHostFree(c.h_tot);
-        if (c.ev_info)
-            (void)hipEventDestroy(c.ev_info);
         if (c.h_info)
             (void)hipHostFree(c.h_info);
         delete h;
@@ -519,8 +545,6 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass, const double *d
         return bail(NBODY_EDEVICE);
     c.h_red = reinterpret_cast<double *>(c.h_info + 64);
     c.h_err = reinterpret_cast<uint32_t *>(c.h_red + 64);
-    if (hipEventCreateWithFlags(&c.ev_info, hipEventDisableTiming) != hipSuccess)
-        return bail(NBODY_EDEVICE);
     if (hipHostMalloc((void **)&c.h_tot, 8 * sizeof(int64_t),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostGetDevicePointer((void **)&c.d_tot, c.h_tot, 0) != hipSuccess)
@@ -601,8 +625,6 @@ void nbody_free(nbody_ctx *ctx)
     (void)prof_collect(ctx->c);
     for (hipEvent_t e : ctx->c.prof_pool)
         (void)hipEventDestroy(e);
-    if (ctx->c.ev_info)
-        (void)hipEventDestroy(ctx->c.ev_info);
     if (ctx->c.h_tot)
         (void)hipHostFree(ctx->c.h_tot);
     if (ctx->c.h_info)
@@ -660,7 +682,7 @@ int nbody_schedule(nbody_ctx *ctx, double t_target, int32_t *d_idx, int64_t *n_a
     Ctx &c = ctx->c;
     if (!d_idx || !n_act || !t_next || !on_grid(t_target, c.cfg.dt_min))
         return fail(c, NBODY_EINVAL, "bad argument");
-    HIPCHK(c, launch_schedule(c, t_target, c.stream));
+    HIPCHK(c, launch_schedule(c, t_target, ++c.sched_seq, c.stream));
     HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(c, hipStreamSynchronize(c.stream));
     *n_act = c.h_info[0];

@@ -180,7 +180,7 @@ __device__ __forceinline__ void sched_scan(const uint64_t *cmin, const int32_t *
                                            uint64_t *tmin, const int64_t *off, int32_t nc,
                                            double t_target, int64_t *chunk_pos, int64_t *seg,
                                            double *tblock, int64_t *info, int64_t *hist,
-                                           const uint32_t *err, int64_t *info_host)
+                                           const uint32_t *err, int64_t *info_host, int64_t seq)
 {
     __shared__ int64_t buf[1024];
     __shared__ int64_t carry;
@@ -279,13 +279,15 @@ __device__ __forceinline__ void sched_scan(const uint64_t *cmin, const int32_t *
         info[5] = big;
         if (info_host) {
             // the same totals straight into host memory (mapped, coherent),
-            // read by the host once an event after this kernel has completed
+            // then the schedule's sequence number with system-scope release
+            // order: the host polls that word and reads the totals after it
             info_host[0] = carry;
             info_host[1] = __double_as_longlong(tmn);
             info_host[2] = pairs;
             info_host[3] = (int64_t)*err;
             info_host[4] = nclus;
             info_host[5] = big;
+            __hip_atomic_store(&info_host[6], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(1024) void sched_head_kernel(
     const int32_t *chunk_cluster, uint64_t *tmin, uint64_t *cmin, int32_t *ccnt,
     unsigned long long *arrive, int64_t n_chunks, const int64_t *off, int32_t nc,
     double t_target, int64_t *chunk_pos, int64_t *seg, double *tblock, int64_t *info,
-    int64_t *hist, const uint32_t *err, int64_t *info_host)
+    int64_t *hist, const uint32_t *err, int64_t *info_host, int64_t seq)
 {
     constexpr int NT = 1024;
     __shared__ uint64_t rv[NT / 64];
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(1024) void sched_head_kernel(
     if (threadIdx.x == 0)
         *arrive = 0ull;
     sched_scan(cmin, ccnt, n_chunks, chunk_cluster, tmin, off, nc, t_target, chunk_pos, seg,
-               tblock, info, hist, err, info_host);
+               tblock, info, hist, err, info_host, seq);
 }
 
 // ordered compaction of the due particles of each chunk
@@ -801,7 +803,7 @@ hipError_t launch_sched_reset(const Ctx &c, hipStream_t s)
 
 // minima, counts and scan: block times, segments, N_act (info) -- the
 // per-cluster minima must be reset (at init, and by every scan after use)
-hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s)
+hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStream_t s)
 {
     hipLaunchKernelGGL(sched_head_kernel, dim3((unsigned)c.n_chunks), dim3(1024), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
@@ -810,7 +812,7 @@ hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s)
                        reinterpret_cast<unsigned long long *>(c.d_info + INFO_ARRIVE),
                        c.n_chunks, (const int64_t *)c.d_off, c.nc, t_target, c.d_chunk_pos,
                        c.d_seg, c.d_tblock, c.d_info, c.d_info + 8, (const uint32_t *)c.d_err,
-                       c.d_tot);
+                       c.d_tot, seq);
     return hipGetLastError();
 }
 
@@ -836,9 +838,9 @@ hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s)
+hipError_t launch_schedule(const Ctx &c, double t_target, int64_t seq, hipStream_t s)
 {
-    hipError_t e = launch_sched_head(c, t_target, s);
+    hipError_t e = launch_sched_head(c, t_target, seq, s);
     return e != hipSuccess ? e : launch_sched_scatter(c, s);
 }
 

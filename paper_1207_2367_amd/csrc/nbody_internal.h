@@ -100,9 +100,9 @@ hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
                        const int32_t *cluster_of, hipStream_t s);
 hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel,
                               double *acc, hipStream_t s);
-hipError_t launch_schedule(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_schedule(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
 hipError_t launch_sched_reset(const Ctx &c, hipStream_t s);
-hipError_t launch_sched_head(const Ctx &c, double t_target, hipStream_t s);
+hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
 hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s);
 hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s);
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
@@ -181,7 +181,9 @@ struct Ctx {
     double *d_phi = nullptr;             // [n] potential scratch (energy)
     // host pinned mirror for small readbacks
     int64_t *h_info = nullptr;
-    int64_t *h_tot = nullptr;            // [8] scheduler totals, written by the GPU (mapped)
+    int64_t *h_tot = nullptr;            // [8] scheduler totals, written by the GPU (mapped):
+                                         // [0..5] totals, [6] sequence number of the schedule
+    int64_t sched_seq = 0;               // sequence number of the last schedule launched
     int64_t *d_tot = nullptr;            // device address of h_tot
     double *h_red = nullptr;
     uint32_t *h_err = nullptr;
@@ -189,7 +191,6 @@ struct Ctx {
     bool prof = false;
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
-    hipEvent_t ev_info = nullptr;        // recorded after the schedule's host copy
     double prof_ms[PH_N] = {0};
     int64_t prof_cnt[PH_N] = {0};
     double prof_pairs = 0.0;
