@@ -226,6 +226,25 @@ typedef struct nbody_launch {
 int nbody_set_launch(nbody_ctx *ctx, const nbody_launch *shape);
 int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape);
 
+/* Device-resident block steps (the small-block regime of paper Sect. 3,
+   last part, where selecting the active set and reducing the split
+   partials cost as much as the evaluation).  For a context with one
+   system, no pinned launch shape and profiling off, nbody_step runs its
+   block steps inside one cooperative launch (64 workgroups, three grid
+   barriers per block step: schedule, prediction, evaluation with split
+   sources, fixed-order reduction and corrector) for as long as every
+   block has at most max_active active particles; a larger block goes
+   through the host-sized path and the loop resumes after it.  Results
+   equal the host-sized path's to the rounding of the split sums (a
+   different launch shape).  max_active < 0 (the default): automatic, i.e.
+   on for systems of up to 8192 bodies with blocks of up to ~2^21 pairs
+   (at least 4 particles), off for larger systems, where the host-sized
+   path is faster; 0: off; > 0: on with that limit (capped by the
+   split-partials capacity).  A grid barrier that
+   waits for more than about two seconds ends the launch with
+   NBODY_EDEVICE instead of hanging.  Returns NBODY_EINVAL for a NULL ctx. */
+int nbody_set_step_loop(nbody_ctx *ctx, int64_t max_active);
+
 /* GPU time per phase of the block step, measured with HIP events on the
    context's stream while profiling is on (phases follow the paper's
    Table 1: 0 active-set selection, 1 prediction, 2 evaluation (force

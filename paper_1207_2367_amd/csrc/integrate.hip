@@ -12,7 +12,7 @@
 #include <cfloat>
 #include <cmath>
 
-#include "nbody_internal.h"
+#include "force_body.h"
 
 namespace nb {
 
@@ -67,6 +67,9 @@ __device__ uint32_t block_dt(double crit, double dt_old, double t_new, double t_
 // Taylor series of paper Sect. 3 item 1 (Horner form) to the source
 // records.  T is the block time of the particle's cluster, or its own time
 // (h = 0: the records are the stored state) when own_time is set.
+__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, const JRecF64 &jd,
+                                       int prec, int64_t n, int64_t i, double h);
+
 __device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
                                          const JRecF64 &jd, int prec, int64_t n,
                                          const double *Tc, const int32_t *cluster_of,
@@ -74,14 +77,20 @@ __device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
 {
     if (i >= n)
         return;
-    const double ti = st.t[i];
     double h = 0.0;
     if (!own_time) {
         const double T = Tc[cluster_of ? cluster_of[i] : 0];
         if (!(T < DBL_MAX))
             return;  // cluster has reached the target: not a source this step
-        h = T - ti;
+        h = T - st.t[i];
     }
+    pack_h(st, jm, jd, prec, n, i, h);
+}
+
+// the records of particle i advanced by h from its own time
+__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, const JRecF64 &jd,
+                                       int prec, int64_t n, int64_t i, double h)
+{
     double xp[3], vp[3], ap[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -348,18 +357,26 @@ __global__ __launch_bounds__(1024) void sched_head_kernel(
 }
 
 // ordered compaction of the due particles of each chunk
+__device__ __forceinline__ void scatter_range(const double *t, const double *dt, double T,
+                                              int64_t b, int64_t e, int64_t pos, int32_t *act);
+
 __device__ __forceinline__ void scatter_chunk(const double *t, const double *dt,
                                               const int64_t *chunk_begin,
                                               const int32_t *chunk_cluster,
                                               const double *tblock, const int64_t *chunk_pos,
                                               int32_t *act, int64_t q)
 {
-    __shared__ int wsum[TPB / 64];
     const double T = tblock[chunk_cluster[q]];
     if (!(T < DBL_MAX))
         return;
-    const int64_t b = chunk_begin[q], e = chunk_begin[q + 1];
-    int64_t pos = chunk_pos[q];
+    scatter_range(t, dt, T, chunk_begin[q], chunk_begin[q + 1], chunk_pos[q], act);
+}
+
+// the due particles of [b, e) in ascending order to act[pos ...]
+__device__ __forceinline__ void scatter_range(const double *t, const double *dt, double T,
+                                              int64_t b, int64_t e, int64_t pos, int32_t *act)
+{
+    __shared__ int wsum[TPB / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t base = b; base < e; base += TPB) {
         const int64_t i = base + threadIdx.x;
@@ -592,6 +609,28 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
 // one thread per slot runs the corrector on the sums.  part is the
 // evaluation's [B][10][n_act] buffer (the potential slot is not used).
 constexpr int RC_SLOTS = TPB / 9;
+
+// sum of bc split partials p[0], p[stride], ... in the order b = 0 .. bc-1,
+// 16 loads in flight
+__device__ __forceinline__ double sum_splits(const double *p, int64_t stride, int64_t bc)
+{
+    constexpr int U = 16;
+    double r = 0.0;
+    int64_t b = 0;
+    for (; b + U <= bc; b += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = p[(b + u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            r += v[u];
+    }
+    for (; b < bc; ++b)
+        r += p[b * stride];
+    return r;
+}
+
 __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
     State st, int64_t n, int64_t n_act, const double *part, int32_t B, int nt, ForceWork w,
     const int32_t *cluster_of, double t_target, double eta, double dt_min, double dt_max,
@@ -605,23 +644,7 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
         const int64_t i = w.idx[k];
         const int c = cluster_of ? cluster_of[i] : 0;
         const int64_t bc = splits_used(w.off[c + 1] - w.off[c], B, nt);
-        const double *p = part + (int64_t)q * n_act + k;
-        const int64_t stride = 10 * n_act;
-        constexpr int U = 16;
-        double r = 0.0;
-        int64_t b = 0;
-        for (; b + U <= bc; b += U) {
-            double v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                v[u] = p[(b + u) * stride];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                r += v[u];
-        }
-        for (; b < bc; ++b)
-            r += p[b * stride];
-        sum[q][kl] = r;
+        sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
     }
     __syncthreads();
     if (threadIdx.x < RC_SLOTS && k < n_act) {
@@ -629,6 +652,292 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
         const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
         const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
         correct_one(st, n, w.idx[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+    }
+}
+
+// ------------------------------------------- device-resident block steps
+// Block steps of one system whose active sets stay small, run inside one
+// cooperative launch of G workgroups of TPB lanes (all resident at once),
+// with three grid barriers per step:
+//   (1) each workgroup sweeps its own particle range [r0, r1) for the
+//       minimum of t + dt and how many particles reach it -> barrier;
+//   (2) every workgroup reads the G results and forms the block time T,
+//       N_act and the offset of its own due particles (the same decisions
+//       everywhere); all stop together when nothing is due up to the target,
+//       when N_act exceeds a_max (the host path takes that block) or when
+//       the error word is set; otherwise each writes the ascending active
+//       list of its range and predicts its range's sources to T -> barrier;
+//   (3) the evaluation units (i-blocks of LOOP_IB active particles against
+//       one of B source splits) are dealt round-robin -> barrier;
+//   (4) each workgroup sums the split partials of its own range's active
+//       particles in the order b = 0 .. B-1 and runs the corrector on them.
+// The next sweep (1) reads only the workgroup's own range, which only that
+// workgroup has changed in (4): a workgroup barrier is enough there.
+constexpr int LOOP_LPI = 64, LOOP_NW = 4;                 // evaluation shape
+constexpr int LOOP_IB = LOOP_NW * (64 / LOOP_LPI);        // active slots per unit
+constexpr int LOOP_NT = LOOP_NW * 64;                     // sources per tile
+constexpr int LOOP_BMAX = 64;                             // largest split
+constexpr uint32_t LOOP_SPINS = 1u << 21;                 // barrier wait bound (~2 s)
+
+// Grid barrier with one flag word per workgroup (bar[LOOP_FLAG * (1 + w)],
+// a 128-byte line each) and a release word bar[0]: every workgroup releases
+// its writes (device-scope fence) and stores the barrier's epoch into its
+// flag; workgroup 0 polls all flags in parallel (one lane per flag), then
+// fences and stores the epoch into the release word, which the others poll.
+// Polls are relaxed loads followed by one acquiring fence, so the wait does
+// not invalidate caches at every poll, and no word is contended by more
+// than one writer.  A wait longer than LOOP_SPINS polls sets ERR_LOOP and
+// returns false (the workgroup then leaves the loop; the others follow at
+// their next barrier), so no wave can wait forever.  Epochs start at 1 in
+// every launch; the host clears the words before it.
+constexpr int LOOP_FLAG = 32;   // uint32 words per flag line
+__device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t *err,
+                                          uint32_t &epoch)
+{
+    __shared__ int ok;
+    const uint32_t e = ++epoch;
+    if (threadIdx.x == 0)
+        ok = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(&bar[LOOP_FLAG * (1 + blockIdx.x)], e, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        for (uint32_t w = threadIdx.x; w < nblk; w += TPB) {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&bar[LOOP_FLAG * (1 + w)], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) != e) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > LOOP_SPINS) {
+                    atomicOr(err, ERR_LOOP);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_store(&bar[0], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > LOOP_SPINS) {
+                atomicOr(err, ERR_LOOP);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// minimum of t + dt over [b, e) (ordered bits) and how many reach it; the
+// result is valid in thread 0
+__device__ __forceinline__ void range_min_count(const double *t, const double *dt, int64_t b,
+                                                int64_t e, uint64_t &v, int &cnt)
+{
+    __shared__ uint64_t rv[TPB / 64];
+    __shared__ int rn[TPB / 64];
+    v = ~0ull;
+    cnt = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += TPB)
+        min_count(v, cnt, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t ov = __shfl_xor(v, m, 64);
+        const int on = __shfl_xor(cnt, m, 64);
+        min_count(v, cnt, ov, on);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rv[threadIdx.x >> 6] = v;
+        rn[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < TPB / 64; ++w)
+            min_count(v, cnt, rv[w], rn[w]);
+    __syncthreads();
+}
+
+// workgroup-wide minimum / sum, returned to every lane
+__device__ __forceinline__ uint64_t block_min_u64(uint64_t v)
+{
+    __shared__ uint64_t r[TPB / 64];
+    v = wave_min_u64(v);
+    if ((threadIdx.x & 63) == 0)
+        r[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t m = r[0];
+    for (int w = 1; w < TPB / 64; ++w)
+        m = r[w] < m ? r[w] : m;
+    __syncthreads();
+    return m;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v)
+{
+    __shared__ int64_t r[TPB / 64];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0)
+        r[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t s = 0;
+    for (int w = 0; w < TPB / 64; ++w)
+        s += r[w];
+    __syncthreads();
+    return s;
+}
+
+template <int PREC>
+__device__ __forceinline__ const typename Smem<PREC>::R &loop_records(const JRecMixed &jm,
+                                                                      const JRecF64 &jd)
+{
+    if constexpr (std::is_same<typename Smem<PREC>::R, JRecMixed>::value)
+        return jm;
+    else
+        return jd;
+}
+
+// res (mapped host memory): [0] block steps, [1] sum of N_act, [2] sum of
+// N_act * n, [3] reason (LOOP_DONE, LOOP_BIG, LOOP_ERR), [4] N_act of the
+// block it stopped at, then [7] = seq with system-scope release order.
+template <int PREC, bool EPS0>
+__global__ __launch_bounds__(TPB) void step_loop_kernel(
+    State st, JRecMixed jm, JRecF64 jd, int prec, int64_t n, double eps2, double t_target,
+    double eta, double dt_min, double dt_max, int64_t a_max, int32_t *act, double *part,
+    int64_t *seg, const int64_t *off, uint64_t *wmin, int32_t *wcnt, uint32_t *bar,
+    uint32_t *err, int64_t *hist, int64_t *res, int64_t seq)
+{
+    __shared__ double sum[9][RC_SLOTS];
+    const auto &J = loop_records<PREC>(jm, jd);
+    const uint32_t G = gridDim.x;
+    const int64_t P = (n + G - 1) / G;
+    const int64_t r0 = (int64_t)blockIdx.x * P < n ? (int64_t)blockIdx.x * P : n;
+    const int64_t r1 = r0 + P < n ? r0 + P : n;
+    int64_t steps = 0, act_sum = 0, pairs = 0, stop_n = 0;
+    int reason = 0;
+    uint32_t epoch = 0;
+
+    uint64_t v;
+    int cnt;
+    range_min_count(st.t, st.dt, r0, r1, v, cnt);
+    if (threadIdx.x == 0) {
+        wmin[blockIdx.x] = v;
+        wcnt[blockIdx.x] = cnt;
+    }
+    for (;;) {
+        if (!grid_sync(bar, G, err, epoch)) {
+            reason = LOOP_ERR;
+            break;
+        }
+        // (2) block time, N_act and this workgroup's offset, everywhere alike
+        uint64_t tv = ~0ull;
+        for (uint32_t w = threadIdx.x; w < G; w += TPB) {
+            const uint64_t x = wmin[w];
+            tv = x < tv ? x : tv;
+        }
+        const uint64_t T_bits = block_min_u64(tv);
+        int64_t tot = 0, before = 0;
+        for (uint32_t w = threadIdx.x; w < G; w += TPB)
+            if (wmin[w] == T_bits) {
+                tot += wcnt[w];
+                before += w < blockIdx.x ? wcnt[w] : 0;
+            }
+        const int64_t n_act = block_sum_i64(tot);
+        const int64_t first = block_sum_i64(before);
+        const double T = __longlong_as_double((long long)T_bits);
+        if (*(volatile uint32_t *)err != 0)
+            reason = LOOP_ERR;
+        else if (n_act == 0 || !(T <= t_target))
+            reason = LOOP_DONE;
+        else if (n_act > a_max)
+            reason = LOOP_BIG;
+        if (reason) {
+            stop_n = n_act;
+            break;
+        }
+        const int64_t mine = wmin[blockIdx.x] == T_bits ? (int64_t)wcnt[blockIdx.x] : 0;
+        if (mine > 0)
+            scatter_range(st.t, st.dt, T, r0, r1, first, act);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += TPB)
+            pack_h(st, jm, jd, prec, n, i, T - st.t[i]);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            seg[0] = 0;
+            seg[1] = n_act;
+            int bb = 0;
+            while ((int64_t(1) << (bb + 1)) <= n_act)
+                ++bb;
+            atomicAdd((unsigned long long *)&hist[bb], 1ull);
+        }
+        ++steps;
+        act_sum += n_act;
+        pairs += n_act * n;
+        if (!grid_sync(bar, G, err, epoch)) {
+            reason = LOOP_ERR;
+            break;
+        }
+        // (3) evaluation units: i-block g against split b
+        const int64_t n_ib = (n_act + LOOP_IB - 1) / LOOP_IB;
+        int64_t B = 1;
+        while (B * 2 <= LOOP_BMAX && B * 2 * n_ib <= 2 * (int64_t)G && B * 2 * LOOP_NT <= n)
+            B *= 2;
+        ForceWork w{};
+        w.idx = act;
+        w.seg = seg;
+        w.off = off;
+        w.split = (int32_t)B;
+        w.nc = 1;
+        w.n_blocks = n_ib;
+        const ForceOut none{};
+        for (int64_t u = blockIdx.x; u < n_ib * B; u += G)
+            force_block<PREC, LOOP_LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2,
+                                                                u % n_ib, (int)(u / n_ib));
+        if (!grid_sync(bar, G, err, epoch)) {
+            reason = LOOP_ERR;
+            break;
+        }
+        // (4) this range's active particles: split sums (fixed order) and
+        // the corrector, RC_SLOTS particles per pass
+        const int64_t bc = splits_used(n, B, LOOP_NT);
+        const int q = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
+        for (int64_t k0 = first; k0 < first + mine; k0 += RC_SLOTS) {
+            const int64_t k = k0 + kl;
+            const bool in = k < first + mine;
+            if (q < 9 && in)
+                sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
+            __syncthreads();
+            if (threadIdx.x < RC_SLOTS && in) {
+                const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
+                const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
+                const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
+                correct_one(st, n, act[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+            }
+            __syncthreads();
+        }
+        // (1) of the next step, over the range this workgroup just updated
+        range_min_count(st.t, st.dt, r0, r1, v, cnt);
+        if (threadIdx.x == 0) {
+            wmin[blockIdx.x] = v;
+            wcnt[blockIdx.x] = cnt;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        res[0] = steps;
+        res[1] = act_sum;
+        res[2] = pairs;
+        res[3] = reason;
+        res[4] = stop_n;
+        __hip_atomic_store(&res[7], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -842,6 +1151,71 @@ hipError_t launch_schedule(const Ctx &c, double t_target, int64_t seq, hipStream
 {
     hipError_t e = launch_sched_head(c, t_target, seq, s);
     return e != hipSuccess ? e : launch_sched_scatter(c, s);
+}
+
+namespace {
+
+// the loop kernel for a context's precision and softening
+const void *step_loop_fn(const Ctx &c)
+{
+    const bool e0 = c.eps == 0.0;
+    switch (c.cfg.precision) {
+    case NBODY_PREC_FP64:
+        return e0 ? (const void *)step_loop_kernel<PREC_F64, true>
+                  : (const void *)step_loop_kernel<PREC_F64, false>;
+    case NBODY_PREC_FP32PAIR:
+        return e0 ? (const void *)step_loop_kernel<PREC_PAIR32, true>
+                  : (const void *)step_loop_kernel<PREC_PAIR32, false>;
+    default:
+        return e0 ? (const void *)step_loop_kernel<PREC_MIXED, true>
+                  : (const void *)step_loop_kernel<PREC_MIXED, false>;
+    }
+}
+
+}  // namespace
+
+int step_loop_max_grid(const Ctx &c)
+{
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_loop_fn(c), TPB, 0) !=
+            hipSuccess)
+        return 0;
+    if (!coop || per_cu < 1 || cus < 1)
+        return 0;
+    // one workgroup per compute unit: more would only lengthen the barriers
+    return cus < LOOP_GMAX ? cus : LOOP_GMAX;
+}
+
+// Device-resident block steps (see step_loop_kernel).  The caller has reset
+// the barrier words; grid <= step_loop_max_grid(c).
+hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int grid, int64_t seq,
+                            hipStream_t s)
+{
+    State st = c.st;
+    JRecMixed jm = c.jm;
+    JRecF64 jd = c.jd;
+    int prec = c.cfg.precision;
+    int64_t n = c.n;
+    double eps2 = c.eps * c.eps, tt = t_target, eta = c.cfg.eta, dmin = c.cfg.dt_min,
+           dmax = c.cfg.dt_max;
+    int64_t am = a_max, sq = seq;
+    int32_t *act = c.act;
+    double *part = c.part;
+    int64_t *seg = c.d_seg;
+    const int64_t *off = c.d_off;
+    uint64_t *wmin = c.d_loop_min;
+    int32_t *wcnt = c.d_loop_cnt;
+    uint32_t *bar = c.d_loop_bar;
+    uint32_t *err = c.d_err;
+    int64_t *hist = c.d_info + 8;
+    int64_t *res = c.d_tot + 8;
+    void *args[] = {&st,   &jm,  &jd,   &prec, &n,    &eps2, &tt,  &eta,  &dmin, &dmax, &am,
+                    &act,  &part, &seg, &off,  &wmin, &wcnt, &bar, &err,  &hist, &res,  &sq};
+    return hipLaunchCooperativeKernel(step_loop_fn(c), dim3((unsigned)grid), dim3(TPB), args, 0,
+                                      s);
 }
 
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s)

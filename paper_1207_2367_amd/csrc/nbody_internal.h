@@ -105,6 +105,11 @@ hipError_t launch_sched_reset(const Ctx &c, hipStream_t s);
 hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
 hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s);
 hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s);
+hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int grid, int64_t seq,
+                            hipStream_t s);
+// workgroups of the device-resident loop that can be resident at once for
+// the context's precision (0 if the device cannot launch it cooperatively)
+int step_loop_max_grid(const Ctx &c);
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
 hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
@@ -123,7 +128,14 @@ hipError_t launch_check_finite(const Ctx &c, hipStream_t s);
 hipError_t launch_init_dt(const Ctx &c, hipStream_t s);
 
 // Device error word bits (set with atomicOr by kernels).
-enum : uint32_t { ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u };
+enum : uint32_t { ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u, ERR_LOOP = 8u };
+
+// Device-resident block-step loop: why it stopped, and the largest grid.
+enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
+constexpr int LOOP_GMAX = 1024;
+constexpr int LOOP_GRID = 64;            // workgroups the loop uses
+constexpr int64_t LOOP_AUTO_NMAX = 8192; // automatic mode: systems up to this size
+constexpr int64_t LOOP_BAR_WORDS = 32 * (LOOP_GMAX + 1);   // release word + one flag line each
 
 // Schedule scratch: chunk table built at init (a chunk never spans two
 // clusters), per-cluster block times and active segments.
@@ -184,6 +196,12 @@ struct Ctx {
     int64_t *h_tot = nullptr;            // [8] scheduler totals, written by the GPU (mapped):
                                          // [0..5] totals, [6] sequence number of the schedule
     int64_t sched_seq = 0;               // sequence number of the last schedule launched
+    int64_t loop_seq = 0;                // same for the device-resident loop (h_tot[15])
+    int64_t loop_amax = -1;              // loop's largest N_act: -1 automatic, 0 off
+    int loop_grid = -1;                  // its workgroups (-1: not yet queried, 0: none)
+    uint64_t *d_loop_min = nullptr;      // [LOOP_GMAX] per-workgroup minima
+    int32_t *d_loop_cnt = nullptr;       // [LOOP_GMAX] and counts
+    uint32_t *d_loop_bar = nullptr;      // [LOOP_BAR_WORDS] grid barrier words
     int64_t *d_tot = nullptr;            // device address of h_tot
     double *h_red = nullptr;
     uint32_t *h_err = nullptr;

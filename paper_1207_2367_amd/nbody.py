@@ -59,7 +59,8 @@ EXPORTS = [
     "nbody_default_config", "nbody_workspace_bytes", "nbody_init", "nbody_free",
     "nbody_force", "nbody_predict", "nbody_schedule", "nbody_correct", "nbody_block_step",
     "nbody_step", "nbody_get_state", "nbody_set_state", "nbody_energy", "nbody_autotune",
-    "nbody_set_launch", "nbody_get_launch", "nbody_strerror", "nbody_last_error",
+    "nbody_set_launch", "nbody_get_launch", "nbody_set_step_loop", "nbody_strerror",
+    "nbody_last_error",
     "nbody_profile", "nbody_profile_force_log",
 ]
 
@@ -96,6 +97,7 @@ def load():
         "nbody_autotune": (C.c_int, [vp, d]),
         "nbody_set_launch": (C.c_int, [vp, P(Launch)]),
         "nbody_get_launch": (C.c_int, [vp, i64, P(Launch)]),
+        "nbody_set_step_loop": (C.c_int, [vp, i64]),
         "nbody_profile": (C.c_int, [vp, C.c_int, P(ProfileTimes)]),
         "nbody_profile_force_log": (i64, [vp, i64, vp, vp, vp]),
         "nbody_strerror": (C.c_char_p, [C.c_int]),
@@ -260,6 +262,11 @@ class System:
     def set_launch(self, lanes_per_i=0, waves=0, split=0):
         sh = Launch(int(lanes_per_i), int(waves), int(split), 0)
         self._check(load().nbody_set_launch(self.ctx, C.byref(sh)))
+
+    def set_step_loop(self, max_active=-1):
+        """Device-resident block steps of step(): automatic limit (< 0),
+        off (0) or at most max_active active particles per block."""
+        self._check(load().nbody_set_step_loop(self.ctx, int(max_active)))
 
     def profile(self, enable):
         """Start (enable=True, clears) or stop event timing of the phases;
