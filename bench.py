@@ -230,6 +230,14 @@ def summarize_profile(d):
             out.append(f"# dominant kernel {kname} grid {shape[1]} x {shape[2]}: "
                        f"{len(durs)} dispatches in launch order (ms): "
                        + " ".join(f"{x:.4f}" for x in durs))
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        rows = sorted(csv.DictReader(open(f)), key=lambda r: -float(r["TotalDurationNs"]))
+        out.append(f"\n# --stats ({os.path.basename(f)}), top 12 by total time: name, calls, "
+                   "total ms, avg ms")
+        for r in rows[:12]:
+            short = r["Name"].replace("(anonymous namespace)::", "").split("(")[0][:60]
+            out.append(f"{short:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                       f"{float(r['AverageNs']) / 1e6:10.5f}")
     for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         rows = list(csv.DictReader(open(f)))
         per = {}

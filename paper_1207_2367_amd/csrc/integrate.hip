@@ -174,6 +174,39 @@ __device__ __forceinline__ void min_count(uint64_t &v, int &n, uint64_t ov, int 
     }
 }
 
+__global__ __launch_bounds__(TPB) void sched_min(const double *t, const double *dt,
+                                                 const int64_t *chunk_begin,
+                                                 const int32_t *chunk_cluster, uint64_t *tmin,
+                                                 uint64_t *cmin, int32_t *ccnt)
+{
+    __shared__ uint64_t rv[TPB / 64];
+    __shared__ int rn[TPB / 64];
+    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
+    uint64_t v = ~0ull;
+    int n = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += TPB)
+        min_count(v, n, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
+    // xor butterfly: both partners form the same (min, count) of their union
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t ov = __shfl_xor(v, m, 64);
+        const int on = __shfl_xor(n, m, 64);
+        min_count(v, n, ov, on);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rv[threadIdx.x >> 6] = v;
+        rn[threadIdx.x >> 6] = n;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < TPB / 64; ++w)
+            min_count(v, n, rv[w], rn[w]);
+        cmin[blockIdx.x] = v;
+        ccnt[blockIdx.x] = n;
+        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)v);
+    }
+}
+
 __device__ __forceinline__ bool due(double t, double dt, double T) { return t + dt == T; }
 
 // Single workgroup: the due count of every chunk (its count at its minimum
@@ -184,12 +217,13 @@ __device__ __forceinline__ bool due(double t, double dt, double T) { return t + 
 // info[0] = N_act total, info[1] = bits of the earliest block time,
 // info[2] = sum_c N_c * n_act,c, info[3] = device error word snapshot,
 // info[4] = clusters with active particles, info[5] = the largest of them.
-__device__ __forceinline__ void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
-                                           int64_t n_chunks, const int32_t *chunk_cluster,
-                                           uint64_t *tmin, const int64_t *off, int32_t nc,
-                                           double t_target, int64_t *chunk_pos, int64_t *seg,
-                                           double *tblock, int64_t *info, int64_t *hist,
-                                           const uint32_t *err, int64_t *info_host, int64_t seq)
+__device__ __forceinline__ void sched_scan_body(const uint64_t *cmin, const int32_t *ccnt,
+                                                int64_t n_chunks, const int32_t *chunk_cluster,
+                                                uint64_t *tmin, const int64_t *off, int32_t nc,
+                                                double t_target, int64_t *chunk_pos,
+                                                int64_t *seg, double *tblock, int64_t *info,
+                                                int64_t *hist, const uint32_t *err,
+                                                int64_t *info_host, int64_t seq)
 {
     __shared__ int64_t buf[1024];
     __shared__ int64_t carry;
@@ -301,59 +335,16 @@ __device__ __forceinline__ void sched_scan(const uint64_t *cmin, const int32_t *
     }
 }
 
-// The schedule's head, one workgroup of 1024 lanes per chunk: the chunk's
-// minimum of t + dt (as ordered bits; times are >= 0 so the IEEE bits order
-// like the values) and how many of its particles reach it, into cmin/ccnt
-// and the cluster's slot of tmin (a chunk's particles are due exactly when
-// its minimum is the cluster's block time).  The last workgroup to finish
-// (arrival counter, with device-scope fences on both sides so that it sees
-// every other workgroup's results) then runs the scan above and leaves the
-// counter at zero for the next schedule.
-__global__ __launch_bounds__(1024) void sched_head_kernel(
-    const double *t, const double *dt, const int64_t *chunk_begin,
-    const int32_t *chunk_cluster, uint64_t *tmin, uint64_t *cmin, int32_t *ccnt,
-    unsigned long long *arrive, int64_t n_chunks, const int64_t *off, int32_t nc,
-    double t_target, int64_t *chunk_pos, int64_t *seg, double *tblock, int64_t *info,
-    int64_t *hist, const uint32_t *err, int64_t *info_host, int64_t seq)
+__global__ __launch_bounds__(1024) void sched_scan(const uint64_t *cmin, const int32_t *ccnt,
+                                                   int64_t n_chunks, const int32_t *chunk_cluster,
+                                                   uint64_t *tmin, const int64_t *off, int32_t nc,
+                                                   double t_target, int64_t *chunk_pos,
+                                                   int64_t *seg, double *tblock, int64_t *info,
+                                                   int64_t *hist, const uint32_t *err,
+                                                   int64_t *info_host, int64_t seq)
 {
-    constexpr int NT = 1024;
-    __shared__ uint64_t rv[NT / 64];
-    __shared__ int rn[NT / 64];
-    __shared__ int last;
-    const int64_t b = chunk_begin[blockIdx.x], e = chunk_begin[blockIdx.x + 1];
-    uint64_t v = ~0ull;
-    int n = 0;
-    for (int64_t i = b + threadIdx.x; i < e; i += NT)
-        min_count(v, n, (uint64_t)__double_as_longlong(t[i] + dt[i]), 1);
-    // xor butterfly: both partners form the same (min, count) of their union
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t ov = __shfl_xor(v, m, 64);
-        const int on = __shfl_xor(n, m, 64);
-        min_count(v, n, ov, on);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        rv[threadIdx.x >> 6] = v;
-        rn[threadIdx.x >> 6] = n;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < NT / 64; ++w)
-            min_count(v, n, rv[w], rn[w]);
-        cmin[blockIdx.x] = v;
-        ccnt[blockIdx.x] = n;
-        atomicMin((unsigned long long *)&tmin[chunk_cluster[blockIdx.x]], (unsigned long long)v);
-        __threadfence();   // this chunk's results before the arrival
-        last = atomicAdd(arrive, 1ull) == (unsigned long long)(gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();       // every other chunk's results after the arrivals
-    if (threadIdx.x == 0)
-        *arrive = 0ull;
-    sched_scan(cmin, ccnt, n_chunks, chunk_cluster, tmin, off, nc, t_target, chunk_pos, seg,
-               tblock, info, hist, err, info_host, seq);
+    sched_scan_body(cmin, ccnt, n_chunks, chunk_cluster, tmin, off, nc, t_target, chunk_pos, seg,
+                    tblock, info, hist, err, info_host, seq);
 }
 
 // ordered compaction of the due particles of each chunk
@@ -1114,14 +1105,15 @@ hipError_t launch_sched_reset(const Ctx &c, hipStream_t s)
 // per-cluster minima must be reset (at init, and by every scan after use)
 hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStream_t s)
 {
-    hipLaunchKernelGGL(sched_head_kernel, dim3((unsigned)c.n_chunks), dim3(1024), 0, s,
+    hipLaunchKernelGGL(sched_min, dim3((unsigned)c.n_chunks), dim3(TPB), 0, s,
                        (const double *)c.st.t, (const double *)c.st.dt,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
-                       c.d_tmin, c.d_chunk_min, c.d_chunk_cnt,
-                       reinterpret_cast<unsigned long long *>(c.d_info + INFO_ARRIVE),
-                       c.n_chunks, (const int64_t *)c.d_off, c.nc, t_target, c.d_chunk_pos,
-                       c.d_seg, c.d_tblock, c.d_info, c.d_info + 8, (const uint32_t *)c.d_err,
-                       c.d_tot, seq);
+                       c.d_tmin, c.d_chunk_min, c.d_chunk_cnt);
+    hipLaunchKernelGGL(sched_scan, dim3(1), dim3(1024), 0, s, (const uint64_t *)c.d_chunk_min,
+                       (const int32_t *)c.d_chunk_cnt, c.n_chunks,
+                       (const int32_t *)c.d_chunk_cluster, c.d_tmin, (const int64_t *)c.d_off,
+                       c.nc, t_target, c.d_chunk_pos, c.d_seg, c.d_tblock, c.d_info,
+                       c.d_info + 8, (const uint32_t *)c.d_err, c.d_tot, seq);
     return hipGetLastError();
 }
 

@@ -140,9 +140,6 @@ constexpr int64_t LOOP_BAR_WORDS = 32 * (LOOP_GMAX + 1);   // release word + one
 // Schedule scratch: chunk table built at init (a chunk never spans two
 // clusters), per-cluster block times and active segments.
 constexpr int SCHED_CHUNK = 2048;
-// slot of the device info array that holds the schedule's arrival counter
-// (zero between schedules)
-constexpr int INFO_ARRIVE = 56;
 
 // Event-based timing of the phases of a block step (host side).
 enum Phase { PH_SCHED = 0, PH_PREDICT, PH_FORCE, PH_REDUCE, PH_CORRECT, PH_ENERGY, PH_N };
@@ -185,8 +182,7 @@ struct Ctx {
     int64_t *d_seg = nullptr;            // [nc + 1] active segments
     int32_t *d_blk_cluster = nullptr;    // [n / 1 + nc] i-block -> cluster
     int64_t *d_blk_first = nullptr;      // [nc + 1]
-    int64_t *d_info = nullptr;           // [64]: [0..7] step info, [8..47] N_act histogram,
-                                         // [INFO_ARRIVE] the schedule's arrival counter
+    int64_t *d_info = nullptr;           // [64]: [0..7] step info, [8..47] N_act histogram
     uint32_t *d_err = nullptr;           // device error word
     double *d_red = nullptr;             // reduction scratch
     int64_t red_cap = 0;

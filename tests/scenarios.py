@@ -100,13 +100,21 @@ def plummer1k():
         gL0 = np.linalg.norm(s.energy()[2])
         st16, _, _ = _run(s, 1.0 / 16, profile=False)
         dx16 = float(np.abs(s.get_state()["x"].cpu().numpy() - x16).max())
-        st, wall, prof = _run(s, 1.0)
+        st, wall, _ = _run(s, 1.0, profile=False, t_start=1.0 / 16)
         ek, ep, L = s.energy()
         res[name] = {"dE_over_E": (ek + ep - g0) / g0,
                      "dL_over_L": (np.linalg.norm(L) - gL0) / gL0,
                      "block_steps": st16["block_steps"] + st["block_steps"],
                      "max_dx_vs_oracle_t1_16": dx16, "wall_s_1_16_to_1": wall,
                      "interactions": st16["interactions"] + st["interactions"]}
+    # the whole run 0 -> 1 (mixed) with the device-resident block-step loop
+    # (automatic for this size) and with every block on the host-sized path
+    for name, lim in (("loop", -1), ("host_path", 0)):
+        s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+        s.set_step_loop(lim)
+        st, wall, _ = _run(s, 1.0, profile=False)
+        res[f"gpu_mixed_{name}_0_to_1"] = {"wall_s": wall, "block_steps": st["block_steps"],
+                                            "us_per_block_step": wall / st["block_steps"] * 1e6}
     return res
 
 
