@@ -136,15 +136,17 @@ def test_force_clusters(prec):
         _check(prec, force(s, idx), ref, kap)
 
 
-def test_force_many_clusters():
+@pytest.mark.parametrize("n_clusters", [1500, 9000])
+def test_force_many_clusters(n_clusters):
     """1500 clusters of 1-12 bodies (more clusters than the 1024 lanes of
-    the block-table scan), a third of them without active particles: each
-    active particle feels only its own cluster, in a split and an unsplit
-    shape."""
-    rng = np.random.default_rng(1500)
-    sizes = rng.integers(1, 13, 1500)
+    the block-table scan) and 9000 (more than the block table keeps in LDS,
+    so the search runs in global memory), a third of them without active
+    particles: each active particle feels only its own cluster, in a split
+    and an unsplit shape."""
+    rng = np.random.default_rng(n_clusters)
+    sizes = rng.integers(1, 13, n_clusters)
     off = np.concatenate([[0], np.cumsum(sizes)])
-    m, x, v, a = plummer_inputs(int(off[-1]), 1501)
+    m, x, v, a = plummer_inputs(int(off[-1]), n_clusters + 1)
     keep = rng.random(sizes.size) < 2 / 3
     idx = np.sort(np.concatenate([np.arange(off[c], off[c + 1])[rng.random(sizes[c]) < 0.5]
                                   for c in range(sizes.size) if keep[c]]))
