@@ -437,7 +437,7 @@ int run_loop(Ctx &c, double t_target, nbody_step_stats *stats, int *reason)
             a_max *= 2;
     }
     a_max = std::min<int64_t>(a_max, c.part_cap / 64);
-    HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 32 * (c.loop_grid + 1) * sizeof(uint32_t), c.stream));
+    HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 32 * c.loop_grid * sizeof(uint32_t), c.stream));
     const int64_t seq = ++c.loop_seq;
     HIPCHK(c, launch_step_loop(c, t_target, a_max, c.loop_grid, seq, c.stream));
     int64_t r[5];

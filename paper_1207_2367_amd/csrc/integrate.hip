@@ -670,18 +670,19 @@ constexpr int LOOP_NT = LOOP_NW * 64;                     // sources per tile
 constexpr int LOOP_BMAX = 64;                             // largest split
 constexpr uint32_t LOOP_SPINS = 1u << 21;                 // barrier wait bound (~2 s)
 
-// Grid barrier with one flag word per workgroup (bar[LOOP_FLAG * (1 + w)],
-// a 128-byte line each) and a release word bar[0]: every workgroup releases
-// its writes (device-scope fence) and stores the barrier's epoch into its
-// flag; workgroup 0 polls all flags in parallel (one lane per flag), then
-// fences and stores the epoch into the release word, which the others poll.
-// Polls are relaxed loads followed by one acquiring fence, so the wait does
-// not invalidate caches at every poll, and no word is contended by more
-// than one writer.  A wait longer than LOOP_SPINS polls sets ERR_LOOP and
-// returns false (the workgroup then leaves the loop; the others follow at
-// their next barrier), so no wave can wait forever.  Epochs start at 1 in
-// every launch; the host clears the words before it.
+// Grid barrier with one flag word per workgroup (bar[LOOP_FLAG * w], a
+// 128-byte line each): every workgroup releases its writes (device-scope
+// fence), stores the barrier's epoch into its flag, then polls all nblk flags
+// at once (one lane per flag) until each holds this epoch or a later one (a
+// workgroup that already passed stores the next epoch), and fences once to
+// acquire the others' writes.  One store-to-poll hop per barrier, polls are
+// relaxed loads (no cache invalidation per poll) and no word has more than
+// one writer.  A wait longer than LOOP_SPINS polls sets ERR_LOOP and returns
+// false (the workgroup then leaves the loop; the others follow at their
+// next barrier), so no wave can wait forever.  Epochs start at 1 in every
+// launch; the host clears the words before it.  nblk <= TPB.
 constexpr int LOOP_FLAG = 32;   // uint32 words per flag line
+static_assert(LOOP_GRID <= TPB, "the barrier polls one flag per lane");
 __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t *err,
                                           uint32_t &epoch)
 {
@@ -692,31 +693,13 @@ __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        __hip_atomic_store(&bar[LOOP_FLAG * (1 + blockIdx.x)], e, __ATOMIC_RELAXED,
+        __hip_atomic_store(&bar[LOOP_FLAG * blockIdx.x], e, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (blockIdx.x == 0) {
-        for (uint32_t w = threadIdx.x; w < nblk; w += TPB) {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&bar[LOOP_FLAG * (1 + w)], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT) != e) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > LOOP_SPINS) {
-                    atomicOr(err, ERR_LOOP);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            __hip_atomic_store(&bar[0], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else if (threadIdx.x == 0) {
+    if (threadIdx.x < nblk) {
         uint32_t spins = 0;
-        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+        while ((int32_t)(__hip_atomic_load(&bar[LOOP_FLAG * threadIdx.x], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) - e) < 0) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > LOOP_SPINS) {
                 atomicOr(err, ERR_LOOP);

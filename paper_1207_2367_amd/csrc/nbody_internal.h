@@ -135,7 +135,7 @@ enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
 constexpr int LOOP_GMAX = 1024;
 constexpr int LOOP_GRID = 64;            // workgroups the loop uses
 constexpr int64_t LOOP_AUTO_NMAX = 8192; // automatic mode: systems up to this size
-constexpr int64_t LOOP_BAR_WORDS = 32 * (LOOP_GMAX + 1);   // release word + one flag line each
+constexpr int64_t LOOP_BAR_WORDS = 32 * LOOP_GMAX;         // one flag line per workgroup
 
 // Schedule scratch: chunk table built at init (a chunk never spans two
 // clusters), per-cluster block times and active segments.
