@@ -439,7 +439,13 @@ int run_loop(Ctx &c, double t_target, nbody_step_stats *stats, int *reason)
     a_max = std::min<int64_t>(a_max, c.part_cap / 64);
     HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 32 * c.loop_grid * sizeof(uint32_t), c.stream));
     const int64_t seq = ++c.loop_seq;
-    HIPCHK(c, launch_step_loop(c, t_target, a_max, c.loop_grid, seq, c.stream));
+    if (launch_step_loop(c, t_target, a_max, c.loop_grid, seq, c.stream) != hipSuccess) {
+        // the runtime refused the cooperative launch (nothing was enqueued):
+        // clear that error and keep to the host-sized path from now on
+        (void)hipGetLastError();
+        c.loop_grid = 0;
+        return NBODY_OK;
+    }
     int64_t r[5];
     if (int rc = wait_words(c, 8, 5, 15, seq, r))
         return rc;
