@@ -225,8 +225,11 @@ __device__ __forceinline__ void sched_scan_body(const uint64_t *cmin, const int3
                                                 int64_t *hist, const uint32_t *err,
                                                 int64_t *info_host, int64_t seq)
 {
-    __shared__ int64_t buf[1024];
+    // exclusive scan of the due counts, 1024 chunks at a time: inclusive
+    // scan inside each wave by shuffles, then the 16 wave totals
+    __shared__ int64_t wtot[1024 / 64];
     __shared__ int64_t carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0)
         carry = 0;
     __syncthreads();
@@ -234,30 +237,43 @@ __device__ __forceinline__ void sched_scan_body(const uint64_t *cmin, const int3
         const int64_t q = base + threadIdx.x;
         int64_t v = 0;
         if (q < n_chunks) {
-            const uint64_t T = tmin[chunk_cluster[q]];
+            // one system: every chunk belongs to cluster 0 (no dependent load)
+            const uint64_t T = tmin[nc == 1 ? 0 : chunk_cluster[q]];
             if (cmin[q] == T && __longlong_as_double((long long)T) <= t_target)
                 v = ccnt[q];
         }
-        buf[threadIdx.x] = v;
+        int64_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, 64);
+            x += lane >= d ? y : 0;
+        }
+        if (lane == 63)
+            wtot[wave] = x;
         __syncthreads();
-        for (int s = 1; s < 1024; s <<= 1) {
-            const int64_t add = threadIdx.x >= (unsigned)s ? buf[threadIdx.x - s] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += add;
-            __syncthreads();
+        int64_t woff = 0, all = 0;
+        for (int w = 0; w < 1024 / 64; ++w) {
+            const int64_t t = wtot[w];
+            woff += w < wave ? t : 0;
+            all += t;
         }
         if (q < n_chunks)
-            chunk_pos[q] = carry + buf[threadIdx.x] - v;
+            chunk_pos[q] = carry + woff + x - v;
         __syncthreads();
-        if (threadIdx.x == 1023)
-            carry += buf[1023];
+        if (threadIdx.x == 0)
+            carry += all;
         __syncthreads();
     }
     // segment starts: position of the first chunk of each cluster
-    for (int64_t q = threadIdx.x; q < n_chunks; q += 1024) {
-        const int32_t c = chunk_cluster[q];
-        if (q == 0 || chunk_cluster[q - 1] != c)
-            seg[c] = chunk_pos[q];
+    if (nc == 1) {
+        if (threadIdx.x == 0)
+            seg[0] = 0;
+    } else {
+        for (int64_t q = threadIdx.x; q < n_chunks; q += 1024) {
+            const int32_t c = chunk_cluster[q];
+            if (q == 0 || chunk_cluster[q - 1] != c)
+                seg[c] = chunk_pos[q];
+        }
     }
     if (threadIdx.x == 0) {
         seg[nc] = carry;
@@ -522,20 +538,43 @@ __global__ void set_seg_kernel(int64_t *seg, int64_t a, int64_t b)
 // Corrector (paper Sect. 3, item 3), interpolation of crackle, pop and the
 // fifth derivative at the end of the step, and the new block step, for
 // particle i with new a1, j1, s1 evaluated at t_i + dt_i.
-__device__ __forceinline__ void correct_one(State st, int64_t n, int64_t i, const double *a1,
-                                            const double *j1, const double *s1,
-                                            double t_target, double eta, double dt_min,
-                                            double dt_max, uint32_t *err)
+// The stored state of particle i that the corrector reads (loaded apart
+// from the arithmetic so that a kernel can issue these loads early).
+struct OldState {
+    double h, t, a0[3], j0[3], s0[3], v0[3], r0[3];
+};
+
+__device__ __forceinline__ OldState load_old(const State &st, int64_t n, int64_t i)
 {
-    const double h = st.dt[i];
-    const double t_new = st.t[i] + h;
+    OldState o;
+    o.h = st.dt[i];
+    o.t = st.t[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = (int64_t)d * n + i;
+        o.a0[d] = st.acc[e];
+        o.j0[d] = st.jrk[e];
+        o.s0[d] = st.snp[e];
+        o.v0[d] = st.vel[e];
+        o.r0[d] = st.pos[e];
+    }
+    return o;
+}
+
+__device__ __forceinline__ void correct_loaded(State st, int64_t n, int64_t i, const OldState &o,
+                                               const double *a1, const double *j1,
+                                               const double *s1, double t_target, double eta,
+                                               double dt_min, double dt_max, uint32_t *err)
+{
+    const double h = o.h;
+    const double t_new = o.t + h;
     double crk[3], pop[3], a5[3];
     uint32_t bad = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int64_t e = (int64_t)d * n + i;
-        const double a0 = st.acc[e], j0 = st.jrk[e], s0 = st.snp[e];
-        const double v0 = st.vel[e], r0 = st.pos[e];
+        const double a0 = o.a0[d], j0 = o.j0[d], s0 = o.s0[d];
+        const double v0 = o.v0[d], r0 = o.r0[d];
         const double v1 = v0 + h * 0.5 * (a1[d] + a0) - h * h * 0.1 * (j1[d] - j0) +
                           h * h * h * (1.0 / 120) * (s1[d] + s0);
         const double r1 = r0 + h * 0.5 * (v1 + v0) - h * h * 0.1 * (a1[d] - a0) +
@@ -573,6 +612,14 @@ __device__ __forceinline__ void correct_one(State st, int64_t n, int64_t i, cons
         st.dt[i] = dtn;
     if (bad)
         atomicOr(err, bad);
+}
+
+__device__ __forceinline__ void correct_one(State st, int64_t n, int64_t i, const double *a1,
+                                            const double *j1, const double *s1,
+                                            double t_target, double eta, double dt_min,
+                                            double dt_max, uint32_t *err)
+{
+    correct_loaded(st, n, i, load_old(st, n, i), a1, j1, s1, t_target, eta, dt_min, dt_max, err);
 }
 
 __global__ __launch_bounds__(TPB) void correct_kernel(
@@ -631,6 +678,12 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
     const int q = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
     const int64_t k0 = (int64_t)blockIdx.x * RC_SLOTS;
     const int64_t k = k0 + kl;
+    // the lanes that run the corrector load its old state first, so that
+    // those loads overlap the partial sums
+    const bool corr = threadIdx.x < RC_SLOTS && k < n_act;
+    OldState o{};
+    if (corr)
+        o = load_old(st, n, w.idx[k]);
     if (q < 9 && k < n_act) {
         const int64_t i = w.idx[k];
         const int c = cluster_of ? cluster_of[i] : 0;
@@ -638,11 +691,11 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
         sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
     }
     __syncthreads();
-    if (threadIdx.x < RC_SLOTS && k < n_act) {
+    if (corr) {
         const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
         const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
         const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
-        correct_one(st, n, w.idx[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+        correct_loaded(st, n, w.idx[k], o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
     }
 }
 
@@ -887,14 +940,19 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
         for (int64_t k0 = first; k0 < first + mine; k0 += RC_SLOTS) {
             const int64_t k = k0 + kl;
             const bool in = k < first + mine;
+            const bool corr = threadIdx.x < RC_SLOTS && in;
+            OldState o{};
+            if (corr)
+                o = load_old(st, n, act[k]);
             if (q < 9 && in)
                 sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
             __syncthreads();
-            if (threadIdx.x < RC_SLOTS && in) {
+            if (corr) {
                 const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
                 const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
                 const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
-                correct_one(st, n, act[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+                correct_loaded(st, n, act[k], o, a1, j1, s1, t_target, eta, dt_min, dt_max,
+                               err);
             }
             __syncthreads();
         }
