@@ -70,6 +70,23 @@ def plummer(n: int, seed: int, *, mfrac_max: float = 0.999):
     return m, x, v
 
 
+def plummer_bh(n: int, seed: int, m_bh: float = 0.01):
+    """A Plummer sphere of ``n`` stars (as ``plummer``) with a central
+    massive black hole: particle 0 is the hole, of mass ``m_bh`` at rest at
+    the centre, and the stars share the mass 1 - m_bh (their positions and
+    velocities are those of the star-only model, so the system starts close
+    to, not exactly in, equilibrium).  The paper notes that such an object
+    makes the blocks with few particles carry much more of the run time
+    (Sect. 5.5); the hole's mass and placement are this generator's choice.
+    Returns (mass[n+1], pos[n+1,3], vel[n+1,3]) in the centre-of-mass frame."""
+    ms, xs, vs = plummer(n, seed)
+    m = np.concatenate([[m_bh], ms * (1.0 - m_bh)])
+    x = np.concatenate([np.zeros((1, 3)), xs])
+    v = np.concatenate([np.zeros((1, 3)), vs])
+    x, v = _com_frame(m, x, v)
+    return m, x, v
+
+
 def plummer_mean_acc(pos):
     """Acceleration of the smooth Plummer model at ``pos`` (Henon units),
     -r / (r^2 + b^2)^(3/2).  Used only as a realistic synthetic source

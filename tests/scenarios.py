@@ -161,6 +161,23 @@ def _hist_groups(hist):
     return out
 
 
+def _sampled_force_check(m, x, v, smp, prec):
+    """Evaluation of the sampled particles against the oracle on inputs that
+    both take from the generators: positions and velocities of the initial
+    conditions and the smooth Plummer model's acceleration as the sources'
+    acceleration (a context that skips the start-up passes)."""
+    import ics
+    import oracle
+    from paper_1207_2367_amd import System
+    a = ics.plummer_mean_acc(x)
+    s = System(m, x, v, 1e-4, precision=prec, skip_startup=True)
+    s.set_state(a=a)
+    got = [q.cpu().numpy() for q in s.force(smp)]
+    ref = oracle.force(m, x, v, a, 1e-4, smp)
+    del s
+    return got, ref
+
+
 def _by_log2(na_log, pr_log, ms_log):
     """Evaluation launches grouped by floor(log2 N_act): count, pairs, time,
     rate (the efficiency of the batched launches by block size)."""
@@ -181,40 +198,26 @@ def _by_log2(na_log, pr_log, ms_log):
 def plummer1m(t_end=0.125, n=1 << 20):
     """1M-body Plummer sphere (seed 3003), eps 1e-4, eta 0.45, to t = 0.125:
     mixed and FP64 paths, energy error, block N_act histogram, throughput,
-    per-phase time; sampled forces checked against the oracle at t = 0 and
-    at t = 0.125."""
+    per-phase time; sampled forces checked against the oracle on the initial
+    conditions."""
     import ics
     import oracle
     from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
     m, x, v = ics.plummer(n, 3003)
     res = {"config": "plummer1m", "n": n, "t_end": t_end}
-    a0 = None
+    smp = ics.active_subset(n, 256, 31)
+    got, ref = _sampled_force_check(m, x, v, smp, PREC_MIXED)
+    res["force_check_t0"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
+                             zip(("acc", "jrk", "snp", "pot"), got, ref)}
     for name, prec in (("mixed", PREC_MIXED), ("fp64", PREC_FP64)):
         t0 = time.perf_counter()
         s = System(m, x, v, 1e-4, precision=prec)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
-        if a0 is None:
-            a0 = s.get_state()["a"].cpu().numpy()
-        if name == "mixed":
-            # sampled check of the evaluation at t = 0 (stored state = sources)
-            smp = ics.active_subset(n, 256, 31)
-            got = [q.cpu().numpy() for q in s.force(smp)]
-            ref = oracle.force(m, x, v, a0, 1e-4, smp)
-            res["force_check_t0"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
-                                     zip(("acc", "jrk", "snp", "pot"), got, ref)}
         e0 = sum(s.energy()[:2])
         st, wall, prof = _run(s, t_end, pieces=16)
         na_log, pr_log, ms_log = s.force_log()
         e1 = sum(s.energy()[:2])
-        if name == "mixed":
-            # the same sampled check at t_end (synchronized state = sources)
-            st_end = s.get_state()
-            xe, ve, ae = (st_end[q].cpu().numpy() for q in ("x", "v", "a"))
-            got = [q.cpu().numpy() for q in s.force(smp)]
-            ref = oracle.force(m, xe, ve, ae, 1e-4, smp)
-            res["force_check_t_end"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
-                                        zip(("acc", "jrk", "snp", "pot"), got, ref)}
         # share of the evaluation time by the paper's Fig. 7 groups of N_act
         gt = {g: 0.0 for _, _, g in GROUPS}
         for na_, ms_ in zip(na_log, ms_log):
@@ -230,6 +233,55 @@ def plummer1m(t_end=0.125, n=1 << 20):
                      "n_act_log2_hist": st["hist"][:24],
                      "groups": _hist_groups(st["hist"])}
         _log(f"plummer1m {name}: {json.dumps(res[name])[:300]}")
+        del s
+        torch.cuda.empty_cache()
+    return res
+
+
+def bh64k(n=65536, t_end=0.125):
+    """The 65,536-body Plummer sphere of the benchmark alone and around a
+    central black hole of 1 % and 5 % of the mass (paper Sect. 5.5: such an
+    object makes the blocks with few particles carry more of the run time):
+    block steps, N_act groups of the paper's Fig. 7 and their share of the
+    evaluation time, per-phase time and throughput to t = 1/8 (mixed); the
+    hole's and 255 sampled stars' forces against the oracle at t = 0."""
+    import ics
+    from paper_1207_2367_amd import PREC_MIXED, System
+    n = int(n)
+    res = {"config": "bh64k", "n_stars": n, "t_end": t_end}
+    for m_bh in (0.0, 0.01, 0.05):
+        name = f"m_bh={m_bh}"
+        m, x, v = ics.plummer_bh(n, 2002, m_bh) if m_bh > 0 else ics.plummer(n, 2002)
+        if m_bh == 0.01:
+            smp = np.concatenate([[0], ics.active_subset(m.size - 1, 255, 41) + 1])
+            got, ref = _sampled_force_check(m, x, v, smp, PREC_MIXED)
+            res["force_check_t0"] = {q: _err_stats(_rel_rows(g, r)) for q, g, r in
+                                     zip(("acc", "jrk", "snp", "pot"), got, ref)}
+            res["force_check_t0_hole"] = {q: float(_rel_rows(g[:1], r[:1])[0]) for q, g, r in
+                                          zip(("acc", "jrk", "snp", "pot"), got, ref)}
+        s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+        e0 = sum(s.energy()[:2])
+        st, wall, _ = _run(s, t_end, profile=False, pieces=4)
+        e1 = sum(s.energy()[:2])
+        # the same run with the event timing of every phase and the per-launch log
+        s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+        st2, wall2, prof = _run(s, t_end, pieces=4)
+        na_log, pr_log, ms_log = s.force_log()
+        gt = {g: 0.0 for _, _, g in GROUPS}
+        for na_, ms_ in zip(na_log, ms_log):
+            for lo, hi, g in GROUPS:
+                if lo <= na_ <= hi:
+                    gt[g] += float(ms_)
+        tot = sum(gt.values()) or 1.0
+        res[name] = {"dE_over_E": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                     "interactions": st["interactions"], "wall_s": wall,
+                     "us_per_block_step": wall / st["block_steps"] * 1e6,
+                     "G_interactions_per_s": st["interactions"] / wall / 1e9,
+                     "groups": _hist_groups(st["hist"]),
+                     "force_time_share_by_group": {g: gt[g] / tot for g in gt},
+                     "profiled_wall_s": wall2,
+                     "phase_ms": {k: q[0] for k, q in prof.items() if k != "pairs"}}
+        _log(f"bh64k {name}: {json.dumps(res[name])[:300]}")
         del s
         torch.cuda.empty_cache()
     return res
@@ -436,7 +488,7 @@ def blocks32k(n=32768, t_end=1.0):
 
 RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
         "king256": king256, "plummer8m": plummer8m, "bfactor16k": bfactor16k,
-        "etascan": etascan, "blocks32k": blocks32k}
+        "etascan": etascan, "blocks32k": blocks32k, "bh64k": bh64k}
 
 
 def _default(o):

@@ -92,6 +92,35 @@ def test_loop_energy_and_oracle_blocks():
 
 
 @pytest.mark.parametrize("loop", [0, -1], ids=["host", "loop"])
+def test_black_hole_blocks_match_oracle(loop):
+    """4096 Plummer stars around a central black hole of 5 % of the mass
+    (a heavy particle and stiffer central dynamics) to t = 1/16 in FP64, on
+    the host-sized path and through the device loop: the oracle's block
+    steps and interaction count, positions and velocities to roundoff-level
+    drift, the same energy error."""
+    m, x, v = ics.plummer_bh(4096, 1001, 0.05)
+    it = oracle.Integrator(m, x, v, EPS)
+    it.init(1.0 / 16)
+    e0 = sum(it.energy()[:2])
+    err, steps, pairs, hist = it.run(1.0 / 16)
+    assert err == 0
+    de_o = (sum(it.energy()[:2]) - e0) / e0
+    log_case(test="black_hole", loop=loop, n=m.size)
+    s = _system(m, x, v, 1, loop)
+    g0 = sum(s.energy()[:2])
+    st = s.step(1.0 / 16)
+    de_g = (sum(s.energy()[:2]) - g0) / g0
+    g = _state(s)
+    dx = np.abs(g["x"] - it.x).max()
+    dv = np.abs(g["v"] - it.v).max()
+    print(f"loop {loop}: steps oracle {steps} gpu {st['block_steps']}; max|dx| {dx:.2e} "
+          f"max|dv| {dv:.2e}; dE/E {de_o:.4e} {de_g:.4e}")
+    assert st["block_steps"] == steps and st["interactions"] == pairs
+    assert dx < 1e-10 and dv < 1e-9
+    assert abs(de_g - de_o) <= 1e-3 * abs(de_o) + 1e-14
+
+
+@pytest.mark.parametrize("loop", [0, -1], ids=["host", "loop"])
 def test_loop_reports_dtmin(loop):
     """A pair plunging towards each other without softening: the start-up
     passes succeed, then within the first steps the criterion asks for less

@@ -32,6 +32,26 @@ def test_plummer_is_seeded():
     assert not np.array_equal(a[1], c[1])
 
 
+def test_plummer_black_hole():
+    """Particle 0 is the hole (mass m_bh, at the centre of mass, at rest in
+    that frame); the stars are the star-only model's, with the remaining
+    mass, shifted with it."""
+    n, mbh = 2048, 0.01
+    m, x, v = ics.plummer_bh(n, 7, mbh)
+    ms, xs, vs = ics.plummer(n, 7)
+    assert m.shape == (n + 1,) and x.shape == (n + 1, 3)
+    assert m[0] == mbh and abs(m.sum() - 1) < 1e-14
+    assert np.allclose(m[1:], ms * (1 - mbh), rtol=0, atol=1e-18)
+    assert np.abs((m[:, None] * x).sum(0)).max() < 1e-15
+    assert np.abs((m[:, None] * v).sum(0)).max() < 1e-15
+    # the hole sits where the stars' centre of mass was, i.e. at the origin
+    # up to the shift the frame change applies to everything alike
+    shift = x[1:] - xs
+    assert np.abs(shift - shift[0]).max() < 1e-15
+    assert np.abs(x[0] - shift[0]).max() < 1e-15
+    assert np.abs(v[1:] - vs - (v[1:] - vs)[0]).max() < 1e-15
+
+
 def test_king_w0_6_concentration_and_units():
     r, W, M = ics.king_profile(6.0)
     # tidal concentration log10(r_t / r_0) of the W0 = 6 King model ~ 1.25
