@@ -249,7 +249,10 @@ int nbody_set_step_loop(nbody_ctx *ctx, int64_t max_active);
    context's stream while profiling is on (phases follow the paper's
    Table 1: 0 active-set selection, 1 prediction, 2 evaluation (force
    kernel), 3 split-source reduction (of nbody_force; a block step fuses
-   it into 4), 4 correction and new steps, 5 energy).
+   it into 4), 4 correction and new steps, 5 energy; a block step times
+   the compaction of its active list with the prediction, which shares its
+   launch).  While profiling is on, nbody_step does not use the
+   device-resident loop (its phases share one launch).
    nbody_profile(ctx, enable, out): enable = 1 starts (and clears), 0 stops;
    with out != NULL the totals so far are written (synchronizes).  The
    force-kernel launches are also logged one by one: nbody_profile_force_log
