@@ -207,11 +207,12 @@ def summarize_profile(d):
             groups.setdefault(key, []).append(dur)
         tot = sum(sum(v) for v in groups.values())
         out.append(f"# {os.path.basename(f)}: {len(rows)} dispatches, {tot:.3f} ms total")
-        out.append("calls  total_ms   avg_ms     min_ms     max_ms   share  grid_x x grid_y (wg)  kernel")
+        out.append("calls  total_ms   avg_ms  median_ms     min_ms     max_ms   share  grid_x x grid_y (wg)  kernel")
         for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
             short = key[0].replace("(anonymous namespace)::", "").split("(")[0][:90]
-            out.append(f"{len(v):5d} {sum(v):9.3f} {statistics.mean(v):9.5f} {min(v):9.5f} "
-                       f"{max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} ({key[3]})  {short}")
+            out.append(f"{len(v):5d} {sum(v):9.3f} {statistics.mean(v):9.5f} {statistics.median(v):9.5f} "
+                       f"{min(v):9.5f} {max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} "
+                       f"({key[3]})  {short}")
         # the dominant kernel of the bench: the shape of the last mixed-mode
         # evaluation longer than 1 ms (the full active set of the last timed
         # step; later mixed launches are the small energy-error runs); its

@@ -287,6 +287,20 @@ def bh64k(n=65536, t_end=0.125):
     return res
 
 
+def ensemble(t_end=0.25):
+    """The 256-cluster King ensemble of king256 on the GPU alone (autotune,
+    then block steps to t_end; no oracle runs): a short workload to trace."""
+    import ics
+    from paper_1207_2367_amd import PREC_MIXED, System
+    m, x, v, off = ics.king_ensemble()
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED, offsets=off)
+    s.autotune(100.0)
+    st, wall, _ = _run(s, float(t_end), profile=False, pieces=4)
+    return {"config": "ensemble", "n_total": int(m.size), "t_end": float(t_end),
+            "block_steps": st["block_steps"], "interactions": st["interactions"],
+            "wall_s": wall, "us_per_block_step": wall / st["block_steps"] * 1e6}
+
+
 def king256(t_end=1.0):
     """256 King W0 = 6 clusters (Kroupa-like masses), all advanced together in
     one context to t = 1; 12 clusters also integrated by the oracle."""
@@ -488,7 +502,7 @@ def blocks32k(n=32768, t_end=1.0):
 
 RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
         "king256": king256, "plummer8m": plummer8m, "bfactor16k": bfactor16k,
-        "etascan": etascan, "blocks32k": blocks32k, "bh64k": bh64k}
+        "etascan": etascan, "blocks32k": blocks32k, "bh64k": bh64k, "ensemble": ensemble}
 
 
 def _default(o):
