@@ -157,3 +157,34 @@ def test_loop_deterministic_and_resumes():
     for k in sa:
         assert np.array_equal(sa[k], sc[k]), k
         assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_profiling_counts_and_results():
+    """Event timing of the phases (paper Table 1 sections) over a run: one
+    schedule and one predictor launch per block step plus the final empty
+    schedule, one evaluation and one corrector per block step, the logged
+    evaluations' pairs summing to the run's interactions, and the same bits
+    as the same run without profiling on the host-sized path (profiling
+    keeps the device loop off)."""
+    n = 2048
+    m, x, v = ics.plummer(n, 99)
+    a = _system(m, x, v, 0, 0)
+    st_a = a.step(1.0 / 16)
+    b = _system(m, x, v, 0, -1)
+    b.profile(True)
+    st_b = b.step(1.0 / 16)
+    prof = b.profile(False)
+    na, pr, ms = b.force_log()
+    steps = st_b["block_steps"]
+    print({k: v for k, v in prof.items()}, steps)
+    assert steps == st_a["block_steps"] and st_b["interactions"] == st_a["interactions"]
+    assert prof["schedule"][1] == steps + 1 and prof["predict"][1] == steps + 1
+    assert prof["force"][1] == steps and prof["correct"][1] == steps
+    assert prof["energy"][1] == 0
+    assert na.size == steps and int(na.sum()) == st_b["active_total"]
+    assert abs(pr.sum() - st_b["interactions"]) <= 1e-9 * st_b["interactions"]
+    assert abs(prof["pairs"] - st_b["interactions"]) <= 1e-9 * st_b["interactions"]
+    assert np.all(ms > 0) and all(prof[k][0] > 0 for k in ("schedule", "predict", "force", "correct"))
+    sa, sb = _state(a), _state(b)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
