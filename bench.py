@@ -41,7 +41,7 @@ N_ACTS = (1, 64, 1024, 8192, 65536)
 FLOPS_PER_PAIR = 83
 PAPER_FLOPS_PER_PAIR = 97      # the paper's convention (Table 2)
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
-# is switched off in this build, so the attainable FP32 vector rate equals
+# is switched off for every kernel of the library, so the attainable FP32 vector rate equals
 # the FP64 vector rate.
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
 PEAK_FP32_DATASHEET = 157.3                          # counts packed FP32
@@ -294,7 +294,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has "
-              "no multi-GPU mode in this build", file=sys.stderr)
+              "no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -393,7 +393,7 @@ def main():
             "kernel": "evaluation (force) kernel, N_act = N",
             "kernel_avg_ms": round(avg_ms, 5), "flops_per_pair": FLOPS_PER_PAIR,
             "peak_basis": "FP32 vector without packed math: 256 CU x 64 lanes x 2 flop x 2.4 GHz "
-                          "(packed FP32 is disabled in this build)",
+                          "(packed FP32 is disabled in the library)",
             "frac_vs_fp32_datasheet_157.3": round(achieved / PEAK_FP32_DATASHEET, 4),
         },
         "fp64_path": {
