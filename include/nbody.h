@@ -240,7 +240,8 @@ int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape);
    on for systems of up to 8192 bodies with blocks of up to ~2^21 pairs
    (at least 4 particles), off for larger systems, where the host-sized
    path is faster; 0: off; > 0: on with that limit (capped by the
-   split-partials capacity).  A grid barrier that
+   split-partials capacity).  If the runtime refuses the cooperative
+   launch, the context keeps to the host-sized path.  A grid barrier that
    waits for more than about two seconds ends the launch with
    NBODY_EDEVICE instead of hanging.  Returns NBODY_EINVAL for a NULL ctx. */
 int nbody_set_step_loop(nbody_ctx *ctx, int64_t max_active);
