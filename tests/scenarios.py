@@ -433,10 +433,13 @@ def etascan(n=None, precs="mixed,fp64", etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_
     """Energy and angular-momentum error against eta (the paper's Fig. 1
     experiment): Plummer spheres of 2^15 and 2^16 bodies (or n), 10 time
     units, the paper's average of the relative errors at t = 1 .. 10, the
-    mixed and the FP64 paths (or the comma-separated list precs)."""
+    mixed and the FP64 paths (or the comma-separated list precs), at the
+    given eta values (or a comma-separated list)."""
     import ics
     from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, NBodyError, System
     ns = (1 << 15, 1 << 16) if n is None else (int(n),)
+    if isinstance(etas, str):
+        etas = tuple(float(e) for e in etas.split(","))
     modes = [(p, {"mixed": PREC_MIXED, "fp64": PREC_FP64}[p]) for p in precs.split(",")]
     rows = []
     for n in ns:
