@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "nbody_internal.h"
 
@@ -376,16 +378,20 @@ int run_force_init(Ctx &c)
     return NBODY_OK;
 }
 
-// Waits until the schedule launched with sequence number seq has put its
-// totals into the mapped host words, by polling the sequence word (the
-// kernel stores it after the totals with system-scope release order); every
-// 1024 polls the stream is queried, so that a failed or finished stream
-// that never wrote the word ends the wait with an error instead of a hang.
+// Waits until the kernel launched with sequence number seq has put its
+// results into the mapped host words, by polling the sequence word (the
+// kernel stores it after the results with system-scope release order);
+// every 1024 polls the stream is queried, so that a failed or finished
+// stream that never wrote the word ends the wait with an error instead of a
+// hang.  After ~64 k polls (a long kernel, such as the device-resident loop)
+// the host sleeps 20 us between polls instead of spinning.
 int wait_words(Ctx &c, int first, int count, int seq_word, int64_t seq, int64_t *out)
 {
     for (uint32_t spin = 1;; ++spin) {
         if (__atomic_load_n(&c.h_tot[seq_word], __ATOMIC_ACQUIRE) == seq)
             break;
+        if (spin > (1u << 16))
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
         if ((spin & 1023u) == 0) {
             const hipError_t e = hipStreamQuery(c.stream);
             if (e == hipSuccess) {
