@@ -4,11 +4,14 @@
 // the generalized Aarseth criterion (Eqs. indtstp, As) with power-of-two
 // block rules, and the energy / angular-momentum sums (Sect. 5.1).
 //
-// Everything here streams O(N) or O(N_act) FP64 data once, so the bound is
-// HBM bandwidth: kernels read structure-of-arrays state with one particle
-// per lane (coalesced), keep every per-particle temporary in registers and
-// write each output once.  Reductions run in a fixed tree order, so two
-// identical runs give identical bits.
+// These kernels stream O(N) or O(N_act) FP64 data once, so the bound is HBM
+// bandwidth (or, for small sets, latency): they read structure-of-arrays
+// state with one particle per lane (coalesced), keep every per-particle
+// temporary in registers and write each output once.  Reductions run in a
+// fixed tree order, so two identical runs give identical bits.  The file
+// also holds the device-resident loop that runs whole block steps of a
+// small system inside one cooperative launch (step_loop_kernel), with the
+// evaluation body of force_body.h.
 #include <cfloat>
 #include <cmath>
 
