@@ -87,3 +87,11 @@ def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert isinstance(lib.nbody_strerror(code), bytes)
     assert lib.nbody_last_error(None) == b"null context"
+
+
+def test_null_context_calls_are_rejected(lib):
+    from paper_1207_2367_amd import nbody
+    assert lib.nbody_set_step_loop(None, -1) == nbody.EINVAL
+    assert lib.nbody_set_launch(None, None) == nbody.EINVAL
+    assert lib.nbody_step(None, 1.0, None) == nbody.EINVAL
+    assert lib.nbody_autotune(None, 10.0) == nbody.EINVAL
