@@ -128,7 +128,8 @@ void nbody_free(nbody_ctx *ctx);
    of every particle as the source values (positions, velocities and
    accelerations as stored; at a synchronized time this is the predicted
    state).  Any output pointer may be NULL (d_pot) -- acc, jrk and snp are
-   required.  Asynchronous.  Does not change the state.
+   required.  n_act = 0 does nothing and returns NBODY_OK.  Asynchronous.
+   Does not change the state.
    Errors: EINVAL (n_act < 0 or > n, NULL pointer; with cfg->validate the
    index list is checked on the device, the call synchronizes, and an
    out-of-range or non-ascending list gives EINVAL), EDEVICE.           */

@@ -74,6 +74,25 @@ def test_one_particle_clusters(prec):
     assert np.abs(gx - it.x).max() < tol
 
 
+def test_force_empty_and_oversized_lists():
+    """An empty active list does nothing (empty outputs, NBODY_OK); a count
+    above n is rejected before any device work."""
+    import ctypes as C
+
+    from paper_1207_2367_amd import nbody
+    m, x, v, a = plummer_inputs(300, 5)
+    s = gpu_system(m, x, v, a, EPS, 0)
+    got = s.force(np.zeros(0, dtype=np.int64))
+    assert all(q.shape[0] == 0 for q in got)
+    dummy = C.c_void_p(256)
+    assert nbody.load().nbody_force(s.ctx, 301, dummy, dummy, dummy, dummy, None) == nbody.EINVAL
+    assert nbody.load().nbody_force(s.ctx, -1, dummy, dummy, dummy, dummy, None) == nbody.EINVAL
+    # the context still works
+    ref = oracle.force(m, x, v, a, EPS, np.array([3, 7]))
+    got = force(s, np.array([3, 7]))
+    assert np.abs(got[0] - ref[0]).max() < 1e-12 * np.abs(ref[0]).max()
+
+
 @pytest.mark.parametrize("prec", PRECS, ids=IDS)
 def test_coincident_particles(prec):
     """Two distinct bodies at the same place (softened): no mutual force,
