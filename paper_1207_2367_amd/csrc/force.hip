@@ -31,9 +31,11 @@
 //   - grid.y = B splits the sources (chunks of whole tiles; a cluster with
 //     fewer tiles uses fewer splits, the rest exit at once); partial results
 //     go to a [B][10][n_act] buffer that a second kernel sums in fixed order
-//     b = 0 .. B_c-1 (reduce_split here, or the corrector's kernel in a block
-//     step), so the result does not depend on scheduling (no float atomics
-//     anywhere);
+//     b = 0 .. B_c-1 (reduce_split here, the corrector's kernel in a block
+//     step, or the correction phase of the device-resident loop), so the
+//     result does not depend on scheduling (no float atomics anywhere);
+//   - the per-workgroup body (force_block) lives in force_body.h, shared by
+//     the launch kernel here and the device-resident block-step loop;
 //   - a block step's evaluation skips the potential (template flag PHI).
 #include "force_body.h"
 
