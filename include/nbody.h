@@ -117,7 +117,8 @@ int nbody_init(nbody_ctx **out, int64_t n, const double *d_mass,
                const double *d_pos, const double *d_vel, double eps,
                const nbody_config *cfg, void *d_workspace, size_t ws_bytes);
 
-/* Release the host-side context (the workspace stays with the caller). */
+/* Release the host-side context (the workspace stays with the caller);
+   waits for the work queued on the context's stream first.             */
 void nbody_free(nbody_ctx *ctx);
 
 /* Evaluation step alone (paper Sect. 3, item 2, with softening): for the

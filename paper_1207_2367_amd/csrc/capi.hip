@@ -693,6 +693,8 @@ void nbody_free(nbody_ctx *ctx)
 {
     if (!ctx)
         return;
+    // kernels still queued on the stream may write the mapped host words
+    (void)hipStreamSynchronize(ctx->c.stream);
     (void)prof_collect(ctx->c);
     for (hipEvent_t e : ctx->c.prof_pool)
         (void)hipEventDestroy(e);
