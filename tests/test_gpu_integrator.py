@@ -19,7 +19,7 @@ import torch
 
 import ics
 import oracle
-from gpu_helpers import cpu, kappa, log_case, plummer_inputs, rel_err_rows
+from gpu_helpers import abs_err_rows, cpu, log_case, norm_rows, plummer_inputs, term_sums
 
 pytestmark = pytest.mark.gpu
 
@@ -59,11 +59,15 @@ def test_init_parity(prec):
     assert it.init(math.inf) == 0
     s = _system(m, x, v, prec)
     g = {k: cpu(q) for k, q in s.get_state().items()}
-    kap = kappa(m, x, v, it.a, EPS, np.arange(n))
-    # the start-up evaluation is FP64 in both precisions
-    for key, q in (("a", 0), ("jk", 1), ("sn", 2), ("cr", 2)):
-        e = rel_err_rows(g[key], getattr(it, key))
-        assert np.all(e <= 1e-12 * kap[:, q] * (4 if key == "cr" else 1)), (key, e.max())
+    S = term_sums(m, x, v, it.a, EPS, np.arange(n))
+    # the start-up evaluation is FP64 in both precisions: |error| <= 1e-12
+    # times the sum of term magnitudes; the crackle (whose sum has one more
+    # level of terms) 4e-12 of the snap's condition number, relative
+    for key, q in (("a", 0), ("jk", 1), ("sn", 2)):
+        e = abs_err_rows(g[key], getattr(it, key))
+        assert np.all(e <= 1e-12 * S[:, q]), (key, np.nanmax(e))
+    e = abs_err_rows(g["cr"], it.cr) / norm_rows(it.cr)
+    assert np.all(e <= 4e-12 * S[:, 2] / norm_rows(it.sn)), np.nanmax(e)
     assert np.array_equal(g["x"], it.x) and np.array_equal(g["v"], it.v)
     assert np.all(g["t"] == 0)
     nrm = lambda q: np.linalg.norm(q, axis=1)

@@ -276,3 +276,57 @@ def test_clusters_are_independent():
         assert one.run(0.0625)[0] == 0
         assert np.array_equal(one.x, both.x[sl]) and np.array_equal(one.v, both.v[sl])
         assert np.array_equal(one.dt, both.dt[sl])
+
+
+def test_run_counters_hand_case():
+    """orc_run's block-step count, interaction count (N_c times N_act per
+    cluster and step) and log2 N_act histogram against a hand count.  Two
+    clusters (5 and 3 bodies) whose criterion, with eta = 1000, is far above
+    dt_max = 2^-10 = d, so every particle takes the largest step that the
+    block rules allow.  Cluster 0 starts with step d and keeps it (blocks of
+    5 at d, 2d, 3d, 4d).  In cluster 1 two bodies start with d/4 and one
+    with d; a step may only double where the new time is a multiple of
+    twice the old step, so its blocks are d/4 (2 active), d/2 (2), then d,
+    2d, 3d, 4d (3 each).  Every block step takes one block of each cluster
+    still short of the target 4d: 6 block steps, 4 * 5 * 5 + 2 * 3 * 2 +
+    4 * 3 * 3 = 148 interactions, blocks of 5 in bin 2 (4) and of 2 and 3
+    in bin 1 (6); the block times of the whole system (min over the
+    clusters) are d/4, d/2, d, 2d, 3d, 4d with 7, 7, 8, 8, 3, 3 active.
+    A second run to 4.5 d must first halve every step (the target cap):
+    one block step of all 8 bodies, 25 + 9 interactions."""
+    d = 2.0 ** -10
+    m0, x0, v0 = ics.plummer(5, 31)
+    m1, x1, v1 = ics.plummer(3, 32)
+    m = np.concatenate([m0 / 2, m1 / 2])
+    x = np.concatenate([x0, x1 + 10.0])
+    v = np.concatenate([v0, v1])
+    off = [0, 5, 8]
+
+    def fresh():
+        it = oracle.Integrator(m, x, v, 1e-4, eta=1000.0, dt_max=d, offsets=off)
+        assert it.init(4 * d) == oracle.OK
+        it.set_state(dt=np.array([d] * 5 + [d / 4, d, d / 4]), t=np.zeros(8))
+        return it
+
+    it = fresh()
+    err, steps, pairs, hist = it.run(4 * d)
+    assert err == oracle.OK
+    assert np.all(it.t == 4 * d) and np.all(it.dt == d)
+    assert steps == 6
+    assert pairs == 4 * 25 + 2 * 6 + 4 * 9 == 148
+    want = np.zeros(64, dtype=np.int64)
+    want[2], want[1] = 4, 6
+    assert np.array_equal(hist, want)
+    err, steps, pairs, hist = it.run(4.5 * d)
+    assert err == oracle.OK and np.all(it.t == 4.5 * d) and np.all(it.dt == d / 2)
+    assert (steps, pairs) == (1, 34)
+    want = np.zeros(64, dtype=np.int64)
+    want[2], want[1] = 1, 1
+    assert np.array_equal(hist, want)
+
+    it = fresh()
+    seq = [it.block_step(4 * d) for _ in range(6)]
+    assert [s[0] for s in seq] == [oracle.OK] * 6
+    assert [s[1] for s in seq] == [7, 7, 8, 8, 3, 3]
+    assert [s[2] for s in seq] == [d / 4, d / 2, d, 2 * d, 3 * d, 4 * d]
+    assert it.block_step(4 * d)[1] == 0

@@ -36,6 +36,10 @@ MUTANTS = [
     ("block_round_up", "dt = ldexp(1.0, e - 1);", "dt = ldexp(1.0, e);"),
     ("energy_double_count", "for (int64_t j = i + 1; j < j1; ++j)", "for (int64_t j = off[c]; j < j1; ++j) if (j != i)"),
     ("energy_kinetic_half", "k += 0.5 * m[i]", "k += m[i]"),
+    ("run_pairs_nact_squared", "p += (double)cnt[c] * (double)(off[c + 1] - off[c]);",
+     "p += (double)cnt[c] * (double)cnt[c];"),
+    ("run_hist_round_up", "while ((INT64_C(1) << (b + 1)) <= cnt[c])", "while ((INT64_C(1) << b) < cnt[c])"),
+    ("run_counts_before_recap", "    orc_recap(st, t_target);\n    for (;;) {", "    for (;;) {"),
 ]
 
 PINS = ["tests/test_oracle_force.py", "tests/test_oracle_integrator.py"]
