@@ -1,33 +1,44 @@
 #!/usr/bin/env python3
 """Benchmark of the hot path on one MI355X.
 
-Workload (the force microbenchmark configuration): a Plummer sphere of
-N = 65,536 equal masses (seed 2002), softening 1e-4, Henon units.  One
-timed step runs the whole block-step hot path five times, once for each
-active-set size N_act in {1, 64, 1024, 8192, 65,536} (random subsets,
-seed 2003): the times and steps are reset so that exactly that subset is
-due (positions and derivatives carry on), then
-schedule -> predict all N sources -> evaluate a, da, d2a, phi of the active
-particles -> split-source reduction -> corrector + interpolation + new block
-step.  The last block has every particle active, which synchronizes the
-system; the step ends with the FP64 energy / angular momentum sums of the
-synchronized state.
+Workload (the largest single-GPU configuration): a Plummer sphere of
+N = 8,388,608 equal masses (seed 5005), softening 1e-4, Henon units, with
+N_act = 65,536 active particles (seed 5006).  One timed step is one block
+time step of the whole system in which exactly those particles are due:
+schedule (sweep of all N) -> predict all N sources to the block time ->
+evaluate a, da, d2a of the active particles against all N sources (mixed
+precision) -> split-source reduction -> corrector + interpolation of the
+higher derivatives + new block steps.  Before each step the times and
+steps of all particles are reset (two device copies, inside the timed
+region) so that the same particles are due again; positions and
+derivatives carry on.
 
-value = force interactions (N * N_act summed over the five blocks) per
-second of wall time over the timed steps, inputs resident in HBM.
+Preparation (not timed): the state starts from the generator (positions,
+velocities, the smooth Plummer acceleration as every source's
+acceleration); one evaluation of the active set against all sources then
+gives those particles consistent a, da, d2a (the start-up passes of a full
+initialization are two N^2 FP64 evaluations, minutes at this size).  That
+first evaluation is also checked against the oracle on sampled particles.
 
-Also reported: the same for the all-FP64 path and the FP32-pair mode and
-the speedups; the energy error of the three on the 1024-body Plummer run to
-t = 1 (eta = 0.45); the
-per-phase GPU time; the roofline of the dominant kernel (the evaluation
-kernel at N_act = N, timed with HIP events on its stream); and the CPU
-oracle timed on a bounded sample of the same step.
+value = N * N_act * steps / wall time of the timed steps (inputs resident in
+HBM), in G interactions/s.
+
+Also reported: the same step in the FP64 and FP32-pair modes and the
+speedups; the FP64 energy / angular-momentum pass (once, on the synchronized
+prepared state, N^2/2 pairs); the energy error of the three modes on the
+65,536-body sphere integrated to t = 1/8 ("at equal Delta E / E"); the
+65,536-body force-microbenchmark sizes N_act = 1 ... 65,536 (kernel times
+and per-particle errors against the oracle); the roofline of the dominant
+kernel (the mixed evaluation of the timed steps, HIP events on its stream);
+and the CPU oracle timed on a bounded sample of the same block step, on all
+host cores and on one.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,36 +46,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "G interactions/s (acc+jerk+snap), mixed vs FP64 at equal ΔE/E; % VALU peak"
-N_ACTS = (1, 64, 1024, 8192, 65536)
+EPS = 1e-4
+N_BIG, NACT_BIG, SEED_BIG, SEED_SUB = 1 << 23, 65536, 5005, 5006
+N_MICRO, SEED_MICRO, SEED_MICRO_SUB = 65536, 2002, 2003
+MICRO_NACTS = (1, 64, 1024, 8192, 65536)
+DT_ACTIVE, DT_REST = 2.0 ** -10, 1.0 / 16
 # algorithmic flops per pair (FMA = 2, rsqrt = 4; the count of the method's
 # difference, distance, rsqrt, alpha/beta, A/J/S and accumulation terms)
 FLOPS_PER_PAIR = 83
 PAPER_FLOPS_PER_PAIR = 97      # the paper's convention (Table 2)
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
-# is switched off for every kernel of the library, so the attainable FP32 vector rate equals
-# the FP64 vector rate.
-PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
-PEAK_FP32_DATASHEET = 157.3                          # counts packed FP32
+# MI355X published vector peaks (TFLOP/s).  Packed FP32 (which the FP32
+# figure counts) is switched off for every kernel of the library, so an FP32
+# kernel can reach at most half of it: 256 CU x 64 lanes x 2 x 2.4 GHz.
+PEAK_FP32 = 157.3
+PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6
 PEAK_FP64 = 78.6
-# HBM bytes per launch of the dominant kernel (mixed evaluation, N_act = N =
-# 65,536, LPI 1, 4 waves, split 16) from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# passes over `bench.py --profile-pass`, each scaled by what the counter
-# reads for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0): 29.71 MB read +
-# 83.89 MB written (profiles/force_mixed_plummer65536_counters.txt).  Must be
-# re-measured (or set to None) whenever that kernel changes.
-TRAFFIC = 113.6e6
+# HBM bytes of the dominant kernel per launch come from the committed
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this kernel (copy-calibrated)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_mixed_plummer8m_counters.txt")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--n", type=int, default=N_BIG)
+    ap.add_argument("--n-act", type=int, default=NACT_BIG)
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps (no energy pass, micro sizes, energy error)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter passes: a plain copy of a known "
                          "size (counter calibration), then the mixed steps only")
@@ -75,116 +88,223 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-class Workload:
-    """The N-body state and the five prepared active-set schedules."""
+def err_stats(got, ref):
+    """Per-particle relative error ||got_i - ref_i|| / ||ref_i||: max, p99,
+    median and the fraction within 1e-6."""
+    import numpy as np
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    if got.ndim == 1:
+        e = np.abs(got - ref) / np.abs(ref)
+    else:
+        e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)),
+            "median": float(np.median(e)), "frac_le_1e-6": float((e <= 1e-6).mean())}
 
-    def __init__(self, n, precision, autotune):
+
+class BigStep:
+    """The 8M-body system with one active set due at every block step."""
+
+    def __init__(self, gen, precision, check=None):
         import numpy as np
         import torch
 
-        import ics
         from paper_1207_2367_amd import System
-        self.n = n
-        m, x, v = ics.plummer(n, 2002)
-        self.sys = System(m, x, v, 1e-4, precision=precision)
-        if autotune:
-            self.sys.autotune(150.0)
-        self.t0 = torch.zeros(n, dtype=torch.float64, device="cuda")
-        self.dts = []
-        self.sizes = [min(k, n) for k in N_ACTS]
-        rng = np.random.default_rng(2003)
-        for na in self.sizes:
-            dt = np.full(n, 2.0 ** -4)
-            dt[rng.choice(n, na, replace=False)] = 2.0 ** -10
-            self.dts.append(torch.as_tensor(dt, device="cuda"))
-        self.n_act_of = {id(d): na for d, na in zip(self.dts, self.sizes)}
-        self.pairs_per_step = float(sum(n * na for na in self.sizes))
+        m, x, v, a, sub = gen
+        n = self.n = m.shape[0]
+        self.n_act = sub.shape[0]
+        dev = "cuda"
+        self.sys = s = System(m, x, v, EPS, precision=precision, skip_startup=True)
+        a_dev = torch.as_tensor(a, device=dev)
+        s.set_state(a=a_dev)
+        sub_dev = torch.as_tensor(sub, device=dev).to(torch.int32)
+        got = s.force(sub_dev)
+        torch.cuda.synchronize()
+        self.errors = None
+        if check is not None:
+            pos, ref = check
+            self.errors = {q: err_stats(g[pos].cpu().numpy(), r)
+                           for q, g, r in zip(("acc", "jrk", "snp", "pot"), got, ref)}
+        # consistent derivatives for the active particles, the smooth model
+        # for the others; all at t = 0
+        A = a_dev.clone()
+        A[sub_dev.long()] = got[0]
+        JK = torch.zeros_like(A)
+        JK[sub_dev.long()] = got[1]
+        SN = torch.zeros_like(A)
+        SN[sub_dev.long()] = got[2]
+        self.t0 = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.dt = torch.full((n,), DT_REST, dtype=torch.float64, device=dev)
+        self.dt[sub_dev.long()] = DT_ACTIVE
+        s.set_state(a=A, jk=JK, sn=SN, t=self.t0, dt=self.dt)
+        torch.cuda.synchronize()
+        del A, JK, SN, got, a_dev
 
     def step(self):
-        # only t and dt are reset before each block (two device copies): the
-        # particles with the short step are then exactly the prepared subset;
-        # positions and derivatives carry on from the previous blocks (the
-        # sphere moves by ~1e-3 time units per step)
         s = self.sys
-        for dt in self.dts:
-            s.set_state(t=self.t0, dt=dt)
-            na, tb = s.block_step(1.0 / 16)
-            assert na == self.n_act_of[id(dt)]
-        return s.energy()
+        s.set_state(t=self.t0, dt=self.dt)
+        na, _ = s.block_step(DT_REST)
+        assert na == self.n_act, (na, self.n_act)
 
-    def run(self, steps, warmup, profile=False):
+    def run(self, steps, warmup):
         import torch
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        if profile:
-            self.sys.profile(True)
+        self.sys.profile(True)
         t0 = time.perf_counter()
         for _ in range(steps):
             self.step()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        prof = self.sys.profile(False) if profile else None
-        return t1 - t0, prof
+        el = time.perf_counter() - t0
+        prof = self.sys.profile(False)
+        na, _, ms = self.sys.force_log()
+        kms = float(ms[na == self.n_act].mean())
+        phases = {k: round(v[0] / steps, 4) for k, v in prof.items() if k != "pairs"}
+        return el, kms, phases
+
+    def close(self):
+        self.sys.close()
 
 
-def energy_error(precision):
-    """Delta E / E of the 1024-body Plummer sphere integrated to t = 1."""
-    import ics
-    from paper_1207_2367_amd import NBodyError, System
-    m, x, v = ics.plummer(1024, 1001)
-    s = System(m, x, v, 1e-4, precision=precision)
-    e0 = sum(s.energy()[:2])
-    try:
-        st = s.step(1.0)
-    except NBodyError as e:
-        return None, str(e)
-    e1 = sum(s.energy()[:2])
-    return (e1 - e0) / e0, st["block_steps"]
-
-
-def cpu_baseline(n, seconds):
-    """The oracle timed on this host's cores on a bounded sample of the same
-    step: one block step (schedule, predict all N, evaluate the sampled
-    active set, correct it) with a sampled active set sized for ~seconds."""
+def micro_sizes(precisions):
+    """The 65,536-body force microbenchmark: for N_act = 1 ... 65,536 the
+    evaluation kernel's time (nbody_force after the autotuner) and the
+    per-particle errors of up to 512 active particles against the oracle."""
     import numpy as np
+    import torch
 
     import ics
     import oracle
-    m, x, v = ics.plummer(n, 2002)
+    from paper_1207_2367_amd import System
+    n = N_MICRO
+    m, x, v = ics.plummer(n, SEED_MICRO)
     a = ics.plummer_mean_acc(x)
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    out = {}
+    refs = {}
+    for name, prec in precisions:
+        s = System(m, x, v, EPS, precision=prec, skip_startup=True)
+        s.set_state(a=a)
+        s.autotune(150.0)
+        res = {}
+        for na in MICRO_NACTS:
+            idx = ics.active_subset(n, na, SEED_MICRO_SUB)
+            pos = np.arange(na) if na <= 512 else np.sort(
+                np.random.default_rng(na).choice(na, 512, replace=False))
+            if na not in refs:
+                refs[na] = oracle.force(m, x, v, a, EPS, idx[pos])
+            idx_dev = torch.as_tensor(idx, device="cuda").to(torch.int32)
+            got = s.force(idx_dev)
+            s.profile(True)
+            for _ in range(3):
+                s.force(idx_dev)
+            torch.cuda.synchronize()
+            s.profile(False)
+            lna, _, lms = s.force_log()
+            t = float(lms[lna == na].mean())
+            lp = s.get_launch(na)
+            res[str(na)] = {"kernel_ms": round(t, 5),
+                            "G_interactions_per_s": round(na * n / (t * 1e-3) / 1e9, 3),
+                            "launch": {"lanes_per_i": lp[0], "waves": lp[1], "split": lp[2],
+                                       "i_per_lane": lp[3]},
+                            "errors": {q: err_stats(g.cpu().numpy()[pos], r) for q, g, r in
+                                       zip(("acc", "jrk", "snp", "pot"), got, refs[na])}}
+        s.close()
+        out[name] = res
+    return out
 
-    def one(n_act):
-        it = oracle.Integrator(m, x, v, 1e-4)
-        dt = np.full(n, 2.0 ** -4)
-        dt[np.random.default_rng(2003).choice(n, n_act, replace=False)] = 2.0 ** -10
-        it.set_state(a=a, t=np.zeros(n), dt=dt)
-        t0 = time.perf_counter()
-        err, na, tb = it.block_step(1.0 / 16)
-        return time.perf_counter() - t0, na
 
-    dt_cal, _ = one(1024)
-    rate = 1024 * n / max(dt_cal, 1e-6)
-    n_act = int(min(n, max(64, seconds * rate / n)))
-    # repeat the step until about `seconds` of work have been timed
-    el, pairs, reps = 0.0, 0.0, 0
-    while el < 0.8 * seconds or reps == 0:
-        e, na = one(n_act)
-        el += e
-        pairs += float(na) * n
-        reps += 1
-    cpu_model = ""
+def energy_error(precision, n=N_MICRO, t_end=0.125):
+    """Delta E / E of the 65,536-body Plummer sphere (seed 2002, full FP64
+    start-up) integrated to t = 1/8 with block steps (eta 0.45)."""
+    import ics
+    from paper_1207_2367_amd import NBodyError, System
+    m, x, v = ics.plummer(n, SEED_MICRO)
+    s = System(m, x, v, EPS, precision=precision)
+    try:
+        e0 = sum(s.energy()[:2])
+        st = s.step(t_end)
+        e1 = sum(s.energy()[:2])
+        return {"dE_over_E": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                "interactions": st["interactions"]}
+    except NBodyError as e:
+        return {"error": str(e)}
+    finally:
+        s.close()
+
+
+def read_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    counter summary: (bytes, kernel, grid) or None."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    tot, kern = 0.0, None
+    for name in ("FETCH_SIZE", "WRITE_SIZE"):
+        mm = re.search(r"# %s: .*dominant kernel dispatch \d+ \(([^,]+), grid (\d+), "
+                       r"[\d.]+ ms\) [\d.e+]+ KiB -> ([\d.]+) MB per launch" % name, text)
+        if not mm:
+            return None
+        kern = (mm.group(1), int(mm.group(2)))
+        tot += float(mm.group(3)) * 1e6
+    return tot, kern
+
+
+def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
-            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
-        pass
-    return {"value": round(pairs / el / 1e9, 4), "unit": "G interactions/s", "cores": cores,
-            "kind": "oracle", "cpu": cpu_model,
-            "sample": f"{reps} block step(s) of the N={n} Plummer sphere, each with a random active "
-                      f"set of {na} particles (predict all N, evaluate {na} x {n} pairs, correct): "
-                      f"{el:.1f} s in total, FP64 C oracle, OpenMP over active particles"}
+        return ""
+
+
+def cpu_baseline(gen, seconds):
+    """The oracle timed on this host's cores on a bounded sample of the
+    same block step (predict all N, evaluate a sampled active set against
+    all N sources, correct it), on all cores and on one core."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    m, x, v, a, sub = gen
+    n = m.shape[0]
+    it = oracle.Integrator(m, x, v, EPS)
+    gomp = ctypes.CDLL("libgomp.so.1")
+    all_cores = len(os.sched_getaffinity(0))
+
+    def one(n_act):
+        dt = np.full(n, DT_REST)
+        dt[sub[:n_act]] = DT_ACTIVE
+        it.set_state(a=a, jk=0.0, sn=0.0, cr=0.0, t=np.zeros(n), dt=dt)
+        t0 = time.perf_counter()
+        it.block_step(DT_REST)
+        return time.perf_counter() - t0
+
+    res = {}
+    for label, cores in (("all", all_cores), ("one", 1)):
+        gomp.omp_set_num_threads(int(cores))
+        cal = one(16)                      # predict all N + 16 x N pairs
+        per_pair = max(cal - 0.0, 1e-9) / (16.0 * n)
+        na = int(min(sub.shape[0], max(16, seconds / per_pair / n)))
+        el, pairs, reps = 0.0, 0.0, 0
+        while el < 0.8 * seconds or reps == 0:
+            el += one(na)
+            pairs += float(na) * n
+            reps += 1
+        res[label] = {"value": round(pairs / el / 1e9, 4), "cores": cores, "n_act": na,
+                      "reps": reps, "seconds": round(el, 2)}
+    gomp.omp_set_num_threads(all_cores)
+    return {"value": res["all"]["value"], "unit": "G interactions/s", "cores": all_cores,
+            "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "one_core": res["one"],
+            "sample": f"block steps of the N={n} Plummer sphere (seed {SEED_BIG}) in which a "
+                      f"sampled subset of the benchmark's active set is due (predict all N, "
+                      f"evaluate the subset against all N sources, correct): "
+                      f"{res['all']['reps']} x {res['all']['n_act']} active on {all_cores} "
+                      f"cores ({res['all']['seconds']} s), {res['one']['reps']} x "
+                      f"{res['one']['n_act']} active on one core ({res['one']['seconds']} s); "
+                      "FP64 C oracle, OpenMP over active particles"}
 
 
 def summarize_profile(d):
@@ -201,7 +321,6 @@ def summarize_profile(d):
         groups = {}
         for r in rows:
             name = r["Kernel_Name"]
-            grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
             key = (name, r.get("Grid_Size_X", ""), r.get("Grid_Size_Y", ""), r.get("Workgroup_Size_X", ""))
             dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
             groups.setdefault(key, []).append(dur)
@@ -214,9 +333,7 @@ def summarize_profile(d):
                        f"{min(v):9.5f} {max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} "
                        f"({key[3]})  {short}")
         # the dominant kernel of the bench: the shape of the last mixed-mode
-        # evaluation longer than 1 ms (the full active set of the last timed
-        # step; later mixed launches are the small energy-error runs); its
-        # dispatches in launch order (autotune repetitions, warm-up, steps)
+        # evaluation longer than 1 ms; its dispatches in launch order
         mixed = sorted((r for r in rows if "force_kernel<0," in r["Kernel_Name"]),
                        key=lambda r: int(r["Start_Timestamp"]))
         mixed_long = [r for r in mixed
@@ -287,6 +404,14 @@ def summarize_profile(d):
     print("\n".join(out))
 
 
+def make_inputs(n, n_act):
+    import ics
+    m, x, v = ics.plummer(n, SEED_BIG)
+    a = ics.plummer_mean_acc(x)
+    sub = ics.active_subset(n, n_act, SEED_SUB)
+    return m, x, v, a, sub
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
         summarize_profile(sys.argv[2])
@@ -296,75 +421,114 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has "
               "no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
+    log(f"inputs: Plummer N={args.n}, {args.n_act} active")
+    t_in = time.perf_counter()
+    gen = make_inputs(args.n, args.n_act)
+    log(f"inputs ready in {time.perf_counter() - t_in:.1f} s")
+
+    # the oracle first, before anything touches the GPU: the CPU baseline and
+    # the reference values of sampled active particles (for the check of the
+    # first evaluation of each mode)
+    import oracle
+    m, x, v, a, sub = gen
+    cpu = None
+    check = None
+    if not args.profile_pass:
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle)")
+            cpu = cpu_baseline(gen, args.cpu_seconds)
+            log(f"cpu baseline: {cpu['value']} G/s on {cpu['cores']} cores, "
+                f"{cpu['one_core']['value']} G/s on one")
+        pos = np.sort(np.random.default_rng(9).choice(sub.shape[0], min(256, sub.shape[0]),
+                                                      replace=False))
+        t_o = time.perf_counter()
+        check = (pos, oracle.force(m, x, v, a, EPS, sub[pos]))
+        log(f"oracle reference of {pos.size} sampled particles in {time.perf_counter() - t_o:.1f} s")
+
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_1207_2367_amd import PREC_FP32PAIR, PREC_FP64, PREC_MIXED
     from paper_1207_2367_amd import nbody
     if not os.path.exists(nbody.lib_path()):
-        import __graft_entry__
-        __graft_entry__.build()
+        raise RuntimeError("libnbody.so is not built (python __graft_entry__.py build)")
 
     if args.profile_pass:
         # calibration for the HBM counters: copy 1 GiB that is not cache
         # resident (a second buffer is written in between), then the steps
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        b = torch.empty_like(a).fill_(2.0)
-        c = torch.empty_like(a).fill_(3.0)
-        b.copy_(a)
+        ca = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        cb = torch.empty_like(ca).fill_(2.0)
+        cc = torch.empty_like(ca).fill_(3.0)
+        cb.copy_(ca)
         torch.cuda.synchronize()
-        del a, b, c
-        wl = Workload(args.n, PREC_MIXED, not args.no_autotune)
+        del ca, cb, cc
+        wl = BigStep(gen, PREC_MIXED)
         wl.run(args.steps, args.warmup)
+        wl.close()
         torch.cuda.synchronize()
         log("profile pass done")
         return
 
-    log(f"mixed: N={args.n}, warmup {args.warmup}, steps {args.steps}")
-    wl = Workload(args.n, PREC_MIXED, not args.no_autotune)
-    launches = {na: wl.sys.get_launch(na) for na in wl.sizes}
-    el, prof = wl.run(args.steps, args.warmup, profile=True)
-    value = wl.pairs_per_step * args.steps / el / 1e9
-    na_log, pr_log, ms_log = wl.sys.force_log()
-    log(f"mixed: {el / args.steps * 1e3:.3f} ms/step, {value:.2f} G interactions/s")
-
-    # dominant kernel: the evaluation at N_act = N
-    import numpy as np
-    sel = na_log == args.n
-    avg_ms = float(ms_log[sel].mean())
-    pairs = float(args.n) * args.n
-    achieved = FLOPS_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
-    per_nact = {}
-    for na in wl.sizes:
-        s = na_log == na
-        t = float(ms_log[s].mean())
-        per_nact[str(na)] = {"kernel_ms": round(t, 5),
-                             "G_interactions_per_s": round(na * args.n / (t * 1e-3) / 1e9, 3),
-                             "launch": {"lanes_per_i": launches[na][0], "waves": launches[na][1],
-                                        "split": launches[na][2]}}
-    phases = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if k != "pairs"}
+    log(f"mixed: warmup {args.warmup}, steps {args.steps}")
+    wl = BigStep(gen, PREC_MIXED, check)
+    el, avg_ms, phases = wl.run(args.steps, args.warmup)
+    pairs = float(args.n) * args.n_act
+    value = pairs * args.steps / el / 1e9
+    log(f"mixed: {el / args.steps * 1e3:.2f} ms/step, {value:.2f} G interactions/s, "
+        f"kernel {avg_ms:.3f} ms")
+    errors_mixed = wl.errors
+    launch = wl.sys.get_launch(args.n_act)
+    energy = None
+    if not args.no_extras:
+        # a8: the FP64 energy / angular momentum of the whole system, once, on
+        # the synchronized prepared state (N^2 / 2 pairs)
+        wl.sys.set_state(t=wl.t0, dt=wl.dt)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter()
+        ek, ep, L = wl.sys.energy()
+        energy = {"ms": round((time.perf_counter() - t_e) * 1e3, 2), "ekin": ek, "epot": ep,
+                  "L": L, "pairs": float(args.n) * (args.n - 1) / 2}
+        log(f"energy pass: {energy['ms']:.1f} ms")
+    wl.close()
+    del wl
 
     ks = args.fp64_steps or max(2, args.steps // 2)
     other = {}
     for name, prec in (("fp64", PREC_FP64), ("fp32pair", PREC_FP32PAIR)):
-        log(f"{name} path")
-        wd = Workload(args.n, prec, not args.no_autotune)
-        eld, _ = wd.run(ks, 1, profile=True)
-        na_d, _, ms_d = wd.sys.force_log()
-        other[name] = (wd.pairs_per_step * ks / eld / 1e9, float(ms_d[na_d == args.n].mean()))
+        log(f"{name}: warmup 1, steps {ks}")
+        wd = BigStep(gen, prec, check)
+        eld, kmd, phd = wd.run(ks, 1)
+        other[name] = {"value": round(pairs * ks / eld / 1e9, 3), "unit": "G interactions/s",
+                       "ms_per_step": round(eld / ks * 1e3, 3), "kernel_ms": round(kmd, 4),
+                       "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (kmd * 1e-3) / 1e12, 3),
+                       "errors": wd.errors, "phase_ms_per_step": phd}
+        wd.close()
         del wd
-    value_f64, avg_ms_d = other["fp64"]
-    value_p32, avg_ms_p = other["fp32pair"]
+    del gen
 
-    log("energy error, 1024-body Plummer to t = 1")
-    de_mixed, steps_m = energy_error(PREC_MIXED)
-    de_f64, steps_d = energy_error(PREC_FP64)
-    de_p32, steps_p = energy_error(PREC_FP32PAIR)
+    micro = dE = None
+    if not args.no_extras:
+        log("force microbenchmark sizes (65,536 bodies)")
+        micro = micro_sizes((("mixed", PREC_MIXED), ("fp64", PREC_FP64)))
+        log("energy error, 65,536-body Plummer to t = 1/8")
+        dE = {name: energy_error(prec) for name, prec in
+              (("mixed", PREC_MIXED), ("fp64", PREC_FP64), ("fp32pair", PREC_FP32PAIR))}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.n, args.cpu_seconds)
-
+    achieved = FLOPS_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
+    tr = read_traffic()
+    kname = (f"force_kernel<0, {launch[0]}, {launch[1]}, false, false>")
+    traffic = None
+    traffic_note = "no counter summary of this kernel"
+    if tr is not None:
+        if tr[1][0].startswith("void nb::force_kernel<0, %d, %d, false, false>" % launch[:2]) and \
+                tr[1][1] == args.n_act * launch[0]:
+            traffic = round(tr[0])
+            traffic_note = ("FETCH_SIZE + WRITE_SIZE per launch of this kernel, each scaled by "
+                            "what the counter reads for a 1 GiB copy; "
+                            + os.path.relpath(COUNTERS_FILE, ROOT))
+        else:
+            traffic_note = "the counter summary is of another kernel shape"
+    f64 = other["fp64"]
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -372,48 +536,51 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "ms_per_step": round(el / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {
-            "workload": f"Plummer N={args.n} (seed 2002), eps=1e-4, Henon units; one step = "
-                        "block steps with N_act in {1, 64, 1024, 8192, 65536} (schedule, "
-                        "predict, evaluate, reduce, correct, new steps) + FP64 energy of the "
-                        "synchronized state",
-            "n": args.n, "n_act": list(wl.sizes), "precision": "mixed",
+            "workload": f"Plummer N={args.n} (seed {SEED_BIG}), eps=1e-4, Henon units, "
+                        f"{args.n_act} active (seed {SEED_SUB}); one step = one block step "
+                        "(schedule all N, predict all N, evaluate the active set against all "
+                        "N sources, split reduction, correct + interpolate + new steps)",
+            "n": args.n, "n_act": args.n_act, "precision": "mixed",
+            "launch": {"lanes_per_i": launch[0], "waves": launch[1], "split": launch[2],
+                       "i_per_lane": launch[3]},
         },
         "roofline": {
-            "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED, 2),
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4),
-            "traffic": TRAFFIC,
-            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "evaluation (force) kernel, N_act = N",
-            "kernel_avg_ms": round(avg_ms, 5), "flops_per_pair": FLOPS_PER_PAIR,
-            "peak_basis": "FP32 vector without packed math: 256 CU x 64 lanes x 2 flop x 2.4 GHz "
-                          "(packed FP32 is disabled in the library)",
-            "frac_vs_fp32_datasheet_157.3": round(achieved / PEAK_FP32_DATASHEET, 4),
+            "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),
+            "traffic": traffic, "traffic_note": traffic_note,
+            "algorithmic_bytes": args.n * 68 + args.n_act * (4 + 68 + 80),
+            "kernel": kname + f" grid {args.n_act * launch[0]} x {launch[2]}",
+            "kernel_avg_ms": round(avg_ms, 4), "flops_per_pair": FLOPS_PER_PAIR,
+            "peak_basis": "MI355X FP32 vector 157.3 TFLOP/s (counts packed FP32)",
+            "nonpacked_ceiling": {"peak": round(PEAK_FP32_NONPACKED, 2),
+                                  "frac": round(achieved / PEAK_FP32_NONPACKED, 4),
+                                  "note": "packed FP32 is switched off in the library, so "
+                                          "0.5 of 157.3 is this kernel's ceiling"},
         },
-        "fp64_path": {
-            "value": round(value_f64, 3), "unit": "G interactions/s",
-            "kernel_ms_at_N": round(avg_ms_d, 5),
-            "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12, 3),
-            "frac_fp64_peak": round(FLOPS_PER_PAIR * pairs / (avg_ms_d * 1e-3) / 1e12 / PEAK_FP64, 4),
-        },
-        "fp32pair_path": {
-            "value": round(value_p32, 3), "unit": "G interactions/s",
-            "kernel_ms_at_N": round(avg_ms_p, 5),
-            "kernel_tflops": round(FLOPS_PER_PAIR * pairs / (avg_ms_p * 1e-3) / 1e12, 3),
-        },
-        "speedup_mixed_vs_fp64": round(value / value_f64, 3),
-        "kernel_speedup_mixed_vs_fp64": round(avg_ms_d / avg_ms, 3),
-        "kernel_speedup_fp32pair_vs_fp64": round(avg_ms_d / avg_ms_p, 3),
-        "dE_over_E_plummer1024_t1": {"mixed": de_mixed, "fp64": de_f64, "fp32pair": de_p32,
-                                     "block_steps": [steps_m, steps_d, steps_p]},
+        "errors_vs_oracle": {"sampled_active": 0 if check is None else int(check[0].size),
+                             "mixed": errors_mixed, "fp64": f64["errors"],
+                             "fp32pair": other["fp32pair"]["errors"]},
+        "fp64_path": {k: f64[k] for k in ("value", "unit", "ms_per_step", "kernel_ms",
+                                          "kernel_tflops")}
+                     | {"frac_fp64_peak": round(f64["kernel_tflops"] / PEAK_FP64, 4)},
+        "fp32pair_path": {k: other["fp32pair"][k] for k in ("value", "unit", "ms_per_step",
+                                                              "kernel_ms", "kernel_tflops")},
+        "speedup_mixed_vs_fp64": round(value / f64["value"], 3),
+        "kernel_speedup_mixed_vs_fp64": round(f64["kernel_ms"] / avg_ms, 3),
+        "kernel_speedup_fp32pair_vs_fp64": round(f64["kernel_ms"] / other["fp32pair"]["kernel_ms"], 3),
+        "dE_over_E_plummer65536_t0.125": dE,
+        "energy_pass_8m": energy,
+        "micro_plummer65536": micro,
         "paper_equiv_gflops": round(value * PAPER_FLOPS_PER_PAIR, 1),
-        "per_n_act": per_nact,
+        "paper_context": "about 4.1 G interactions/s per NVIDIA Tesla M2070 (400 GFLOPS at 97 "
+                         "flops per interaction, 8M-body Plummer run)",
         "phase_ms_per_step": phases,
         "cpu_baseline": cpu,
     }

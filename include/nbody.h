@@ -43,11 +43,14 @@ extern "C" {
 /* Precision of the evaluation (the state, predictor, corrector, step
    criterion and energy are FP64 in every mode):
    MIXED (default): r_j - r_i, r^2, 1/r (FP32 rsqrt seed + one FP64 Newton
-     step), the acceleration and potential terms and their sums in FP64;
-     jerk and snap terms in FP32 with compensated (double-single)
-     accumulation.  The step criterion's fifth-derivative estimate
-     amplifies the acceleration's absolute error by ~720/h^5, which with
-     FP32 acceleration terms can drive steps down to dt_min.
+     step), the acceleration, jerk and potential terms and their sums in
+     FP64; the snap terms in FP32 with compensated (double-single)
+     accumulation.  Acceleration, jerk and potential are within 1e-6
+     (relative, per particle) of an FP64 evaluation; the snap within about
+     1e-6 times the condition number of its sum.  The step criterion's
+     fifth-derivative estimate amplifies the acceleration's absolute error
+     by ~720/h^5, which with FP32 acceleration terms can drive steps down
+     to dt_min.
    FP32PAIR: every pair term in FP32 (from the FP64 difference r_j - r_i)
      with compensated accumulation -- fastest; safe only where steps stay
      near their natural length.
@@ -133,7 +136,9 @@ void nbody_free(nbody_ctx *ctx);
    Does not change the state.
    Errors: EINVAL (n_act < 0 or > n, NULL pointer; with cfg->validate the
    index list is checked on the device, the call synchronizes, and an
-   out-of-range or non-ascending list gives EINVAL), EDEVICE.           */
+   out-of-range or non-ascending list gives EINVAL; without it an index
+   outside [0, n) is skipped -- its outputs are not written -- and
+   reported as EINVAL by the next call that synchronizes), EDEVICE.     */
 int nbody_force(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx,
                 double *d_acc, double *d_jrk, double *d_snp, double *d_pot);
 
@@ -160,7 +165,9 @@ int nbody_schedule(nbody_ctx *ctx, double t_target, int32_t *d_idx,
    whole active block of their cluster) with new acceleration, jerk and
    snap d_acc/d_jrk/d_snp[n_act][3] evaluated at their block time
    t_i + dt_i.  t_target caps the new steps.  Synchronizes.
-   Errors: EINVAL, EDEVICE, EDTMIN, ENONFINITE.                          */
+   Errors: EINVAL (also an index outside [0, n), which is skipped; with
+   cfg->validate the list is checked for range and order before any
+   change), EDEVICE, EDTMIN, ENONFINITE.                                 */
 int nbody_correct(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx,
                   double t_target, const double *d_acc, const double *d_jrk,
                   const double *d_snp);
@@ -200,8 +207,10 @@ int nbody_set_state(nbody_ctx *ctx, const double *d_pos, const double *d_vel,
 /* Energy and angular momentum in FP64 (paper Sect. 5.1): kinetic energy,
    softened potential energy -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2) (pairs
    within a cluster), and L = sum m r x v, summed over all clusters, from
-   the stored state.  Meaningful when every particle is at the same time.
-   Synchronizes.  Errors: EDEVICE.                                       */
+   the stored state.  Requires every particle of a cluster to be at one
+   time (clusters may differ).  Synchronizes.
+   Errors: ESTATE (particles of a cluster at different times; nothing is
+   computed), EDEVICE.                                                   */
 int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3]);
 
 /* Measure launch shapes of the force kernel for active-set sizes
@@ -215,18 +224,32 @@ int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3]);
 int nbody_autotune(nbody_ctx *ctx, double max_ms);
 
 /* Force kernel launch shape: lanes per active particle (1..64, a power of
-   two), waves per workgroup (1, 2 or 4) and split-source factor (>= 1).
-   nbody_set_launch pins a shape for every later force evaluation (0 in
-   any field restores automatic choice); nbody_get_launch reports the
+   two), waves per workgroup (1, 2 or 4), split-source factor (>= 1) and
+   active particles per group of lanes_per_i lanes (1 or 2, 2 only with
+   lanes_per_i <= 4: each source read from LDS then serves two pairs; 0
+   means 1).  nbody_set_launch pins a shape for every later force
+   evaluation (0 in lanes_per_i, waves or split restores automatic choice;
+   EINVAL for a shape outside these ranges); nbody_get_launch reports the
    shape that automatic choice takes for n_act active particles.       */
 typedef struct nbody_launch {
     int32_t lanes_per_i;
     int32_t waves;
     int32_t split;
-    int32_t reserved;
+    int32_t i_per_lane;
 } nbody_launch;
 int nbody_set_launch(nbody_ctx *ctx, const nbody_launch *shape);
 int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape);
+
+/* The autotuner's table, so that a measured table can be stored by the
+   caller and reused (the same shapes, hence the same bits, in every run):
+   entry b is the shape for active sets 2^b <= N_act < 2^(b+1), all-zero
+   where no shape was measured (the launch rule applies).
+   nbody_get_tuning copies up to max entries and returns the number of
+   entries (0 before nbody_autotune), or EINVAL.  nbody_set_tuning replaces
+   the table with count (<= 40) entries; each must be all-zero or a valid
+   shape (as for nbody_set_launch), else EINVAL and the table is kept.  */
+int nbody_get_tuning(nbody_ctx *ctx, nbody_launch *table, int32_t max);
+int nbody_set_tuning(nbody_ctx *ctx, const nbody_launch *table, int32_t count);
 
 /* Device-resident block steps (the small-block regime of paper Sect. 3,
    last part, where selecting the active set and reducing the split

@@ -104,6 +104,8 @@ int take_err(Ctx &c)
         return fail(c, NBODY_EDTMIN, "a particle needs a step below dt_min");
     if (e & ERR_LOOP)
         return fail(c, NBODY_EDEVICE, "a grid barrier of the device-resident loop timed out");
+    if (e & ERR_STATE)
+        return fail(c, NBODY_ESTATE, "the particles of a cluster are not at one time");
     return fail(c, NBODY_EINVAL, "index list out of range / not ascending, or a particle is past the target time");
 }
 
@@ -133,13 +135,21 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     st.dt = (double *)take(n * d);
     st.mass = (double *)take(n * d);
     JRecMixed jm{};
+    JRecPair32 jp{};
     JRecF64 jd{};
-    if (prec != NBODY_PREC_FP64) {
-        jm.x = (double *)take(n * d);
-        jm.y = (double *)take(n * d);
-        jm.z = (double *)take(n * d);
-        jm.m = (double *)take(n * d);
-        float **fl[6] = {&jm.vx, &jm.vy, &jm.vz, &jm.ax, &jm.ay, &jm.az};
+    if (prec == NBODY_PREC_MIXED) {
+        double **dl[7] = {&jm.x, &jm.y, &jm.z, &jm.m, &jm.vx, &jm.vy, &jm.vz};
+        for (auto p : dl)
+            *p = (double *)take(n * d);
+        float **fl[3] = {&jm.ax, &jm.ay, &jm.az};
+        for (auto p : fl)
+            *p = (float *)take(n * f);
+    } else if (prec == NBODY_PREC_FP32PAIR) {
+        jp.x = (double *)take(n * d);
+        jp.y = (double *)take(n * d);
+        jp.z = (double *)take(n * d);
+        jp.m = (double *)take(n * d);
+        float **fl[6] = {&jp.vx, &jp.vy, &jp.vz, &jp.ax, &jp.ay, &jp.az};
         for (auto p : fl)
             *p = (float *)take(n * f);
     } else {
@@ -173,6 +183,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     if (c) {
         c->st = st;
         c->jm = jm;
+        c->jp = jp;
         c->jd = jd;
         c->part = part;
         c->part_cap = part_cap;
@@ -296,12 +307,12 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     // batched context were measured on batched blocks and are kept.
     if (c.nc > 1 && c.pinned.lpi == 0) {
         if (!has_tuned(c, n_act_typ))
-            while (L.split > 1 && n_act * L.lpi * L.split > (int64_t(1) << 20))
+            while (L.split > 1 && n_act * L.lpi / L.ipt * L.split > (int64_t(1) << 20))
                 L.split >>= 1;
         // a batched block with few active clusters: at least 2^16 lanes,
         // splitting further while every split keeps a tile of the largest
         const int64_t ns = n_src > 0 ? n_src : max_cluster(c);
-        while (n_act * L.lpi * L.split < (int64_t(1) << 16) &&
+        while (n_act * L.lpi / L.ipt * L.split < (int64_t(1) << 16) &&
                ns / ((int64_t)L.split * 2) >= 64 * L.waves &&
                (int64_t)L.split * 2 * n_act <= c.part_cap)
             L.split <<= 1;
@@ -313,6 +324,7 @@ int run_force(Ctx &c, const int32_t *idx, int64_t n_act, int64_t n_act_typ, cons
     w.off = c.d_off;
     w.split = L.split;
     w.nc = c.nc;
+    w.err = c.d_err;
     if (c.nc == 1) {
         w.n_blocks = (n_act + ib - 1) / ib;
     } else {
@@ -344,6 +356,7 @@ int run_force_init(Ctx &c)
     HIPCHK(c, launch_segments(c, nullptr, n, s));
     Launch L = pick_launch(c, c.nc == 1 ? n : std::max<int64_t>(1, n / c.nc), max_cluster(c));
     L.split = 1;
+    L.ipt = 1;   // the start-up kernels take one particle per lane group
     while (n * L.lpi < (int64_t(1) << 18) && L.lpi < 64)
         L.lpi <<= 1;
     const int64_t ib = iblock_size(L);
@@ -775,6 +788,12 @@ int nbody_correct(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx, double t_
     if (n_act < 0 || n_act > c.n || (n_act > 0 && (!d_idx || !d_acc || !d_jrk || !d_snp)) ||
         !on_grid(t_target, c.cfg.dt_min))
         return fail(c, NBODY_EINVAL, "bad argument");
+    if (c.cfg.validate && n_act > 0) {
+        HIPCHK(c, launch_validate_idx(c, n_act, d_idx, c.stream));
+        const int rc = take_err(c);
+        if (rc)
+            return rc;
+    }
     HIPCHK(c, launch_correct(c, n_act, d_idx, t_target, d_acc, d_jrk, d_snp, 3, 1, c.stream));
     return take_err(c);
 }
@@ -873,6 +892,10 @@ int nbody_energy(nbody_ctx *ctx, double *ekin, double *epot, double L[3])
     if (!ctx)
         return NBODY_EINVAL;
     Ctx &c = ctx->c;
+    HIPCHK(c, launch_sync_check(c, c.stream));
+    const int rc = take_err(c);
+    if (rc)
+        return rc;
     HIPCHK(c, launch_energy_pot(c, c.d_phi, c.stream));
     const int rec = prof_begin(c, PH_ENERGY);
     HIPCHK(c, launch_energy_sums(c, c.d_phi, c.d_red + c.red_cap - 8, c.stream));
@@ -901,13 +924,54 @@ int nbody_set_launch(nbody_ctx *ctx, const nbody_launch *shape)
         return NBODY_OK;
     }
     const int l = shape->lanes_per_i;
+    const int ipt = shape->i_per_lane == 0 ? 1 : shape->i_per_lane;
     if (l < 1 || l > 64 || (l & (l - 1)) || (shape->waves != 1 && shape->waves != 2 &&
                                              shape->waves != 4) || shape->split < 1 ||
-        shape->split > 65535)
+        shape->split > 65535 || ipt < 1 || ipt > 2 || (ipt == 2 && l > 4))
         return fail(c, NBODY_EINVAL, "bad launch shape");
     c.pinned.lpi = l;
     c.pinned.waves = shape->waves;
     c.pinned.split = shape->split;
+    c.pinned.ipt = ipt;
+    return NBODY_OK;
+}
+
+int nbody_get_tuning(nbody_ctx *ctx, nbody_launch *table, int32_t max)
+{
+    if (!ctx || max < 0 || (max > 0 && !table))
+        return NBODY_EINVAL;
+    const Ctx &c = ctx->c;
+    const int32_t cnt = (int32_t)c.tuned.size();
+    for (int32_t b = 0; b < std::min(cnt, max); ++b) {
+        table[b].lanes_per_i = c.tuned[b].lpi;
+        table[b].waves = c.tuned[b].waves;
+        table[b].split = c.tuned[b].split;
+        table[b].i_per_lane = c.tuned[b].lpi > 0 ? c.tuned[b].ipt : 0;
+    }
+    return cnt;
+}
+
+int nbody_set_tuning(nbody_ctx *ctx, const nbody_launch *table, int32_t count)
+{
+    if (!ctx || count < 0 || count > 40 || (count > 0 && !table))
+        return NBODY_EINVAL;
+    Ctx &c = ctx->c;
+    std::vector<Launch> t(count);
+    for (int32_t b = 0; b < count; ++b) {
+        const nbody_launch &e = table[b];
+        if (e.lanes_per_i == 0 && e.waves == 0 && e.split == 0)
+            continue;   // no tuned shape for this size
+        const int l = e.lanes_per_i;
+        const int ipt = e.i_per_lane == 0 ? 1 : e.i_per_lane;
+        if (l < 1 || l > 64 || (l & (l - 1)) || (e.waves != 1 && e.waves != 2 && e.waves != 4) ||
+            e.split < 1 || e.split > 65535 || ipt < 1 || ipt > 2 || (ipt == 2 && l > 4))
+            return fail(c, NBODY_EINVAL, "bad launch shape in the tuning table");
+        t[b].lpi = l;
+        t[b].waves = e.waves;
+        t[b].split = e.split;
+        t[b].ipt = ipt;
+    }
+    c.tuned = t;
     return NBODY_OK;
 }
 
@@ -930,7 +994,7 @@ int nbody_get_launch(nbody_ctx *ctx, int64_t n_act, nbody_launch *shape)
     shape->lanes_per_i = L.lpi;
     shape->waves = L.waves;
     shape->split = L.split;
-    shape->reserved = 0;
+    shape->i_per_lane = L.ipt;
     return NBODY_OK;
 }
 
@@ -1001,8 +1065,9 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
         double spent = 0.0;
         for (int waves : {4, 2, 1}) {
             for (int lpi = 1; lpi <= 64; lpi <<= 1) {
+              for (int ipt = 1; ipt <= (lpi <= 4 ? 2 : 1); ++ipt) {
                 for (int split = 1; split <= 4096; split <<= 1) {
-                    const int64_t lanes = nt * lpi * split;
+                    const int64_t lanes = nt * lpi * split / ipt;
                     if (lanes < (int64_t(1) << 14) && !(lpi == 64 && split >= nsrc / (64 * waves)))
                         continue;   // too little parallelism (unless nothing more is possible)
                     if (lanes > (int64_t(1) << 22) || split * nt > c.part_cap)
@@ -1014,6 +1079,7 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
                     c.pinned.lpi = lpi;
                     c.pinned.waves = waves;
                     c.pinned.split = split;
+                    c.pinned.ipt = ipt;
                     // one warm-up, then the minimum of 2 timed launches (of 6 when
                     // a launch is shorter than 0.2 ms, where timing noise is
                     // comparable to the differences between shapes)
@@ -1045,6 +1111,9 @@ int nbody_autotune(nbody_ctx *ctx, double max_ms)
                 }
                 if (rc || spent > max_ms)
                     break;
+              }
+              if (rc || spent > max_ms)
+                  break;
             }
             if (rc || spent > max_ms)
                 break;

@@ -66,14 +66,15 @@ __device__ __forceinline__ double pot_tile(const double *sx, const double *sy,
 }
 
 // PHI: also sum the potential (nbody_force, the start-up pass); a block
-// step's evaluation does not need it (the energy has its own pass).
-template <int PREC, int LPI, int NW, bool EPS0, bool PHI>
+// step's evaluation does not need it (the energy has its own pass).  IPT:
+// active particles per lane group.
+template <int PREC, int LPI, int NW, bool EPS0, bool PHI, int IPT>
 __global__ __launch_bounds__(NW * 64) void force_kernel(
     typename Smem<PREC>::R J, ForceWork w, ForceOut out, double *part,
     int64_t n_act_total, double eps2)
 {
-    force_block<PREC, LPI, NW, EPS0, PHI>(J, w, out, part, n_act_total, eps2, blockIdx.x,
-                                          blockIdx.y);
+    force_block<PREC, LPI, NW, EPS0, PHI, IPT>(J, w, out, part, n_act_total, eps2,
+                                               blockIdx.x, blockIdx.y);
 }
 
 // Potential energy of the stored state (paper Sect. 5.1): every unordered
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t 
     const double *p = part + (int64_t)q * n_act + k;
     if (w.off) {
         const int64_t i = w.idx ? (int64_t)w.idx[k] : k;
-        const int c = cluster_of ? cluster_of[i] : 0;
+        // (an index out of range was skipped by the evaluation: any cluster)
+        const int c = cluster_of && i >= 0 && i < w.off[w.nc] ? cluster_of[i] : 0;
         B = (int32_t)splits_used(w.off[c + 1] - w.off[c], B, nt);
     }
     const int64_t stride = 10 * n_act;
@@ -209,39 +211,46 @@ __global__ __launch_bounds__(256) void reduce_split(const double *part, int32_t 
 
 // ---- dispatch table over the template parameters
 using KMixed = void (*)(JRecMixed, ForceWork, ForceOut, double *, int64_t, double);
+using KPair32 = void (*)(JRecPair32, ForceWork, ForceOut, double *, int64_t, double);
 using KF64 = void (*)(JRecF64, ForceWork, ForceOut, double *, int64_t, double);
 
+// Two active particles per lane group are built for 1, 2 and 4 lanes per
+// particle (the large active sets, where the LDS reads per pair matter);
+// smaller sets use one.
 template <int PREC, bool EPS0, int NW, bool PHI>
-auto pick_lpi(int lpi_log2)
+auto pick_lpi(int lpi_log2, int ipt)
 {
-    using K = typename std::conditional<PREC == PREC_MIXED || PREC == PREC_PAIR32, KMixed, KF64>::type;
+    using K = void (*)(typename Smem<PREC>::R, ForceWork, ForceOut, double *, int64_t, double);
     static const K tab[7] = {
-        force_kernel<PREC, 1, NW, EPS0, PHI>,  force_kernel<PREC, 2, NW, EPS0, PHI>,
-        force_kernel<PREC, 4, NW, EPS0, PHI>,  force_kernel<PREC, 8, NW, EPS0, PHI>,
-        force_kernel<PREC, 16, NW, EPS0, PHI>, force_kernel<PREC, 32, NW, EPS0, PHI>,
-        force_kernel<PREC, 64, NW, EPS0, PHI>};
-    return tab[lpi_log2];
+        force_kernel<PREC, 1, NW, EPS0, PHI, 1>,  force_kernel<PREC, 2, NW, EPS0, PHI, 1>,
+        force_kernel<PREC, 4, NW, EPS0, PHI, 1>,  force_kernel<PREC, 8, NW, EPS0, PHI, 1>,
+        force_kernel<PREC, 16, NW, EPS0, PHI, 1>, force_kernel<PREC, 32, NW, EPS0, PHI, 1>,
+        force_kernel<PREC, 64, NW, EPS0, PHI, 1>};
+    static const K tab2[3] = {force_kernel<PREC, 1, NW, EPS0, PHI, 2>,
+                              force_kernel<PREC, 2, NW, EPS0, PHI, 2>,
+                              force_kernel<PREC, 4, NW, EPS0, PHI, 2>};
+    return ipt == 2 && lpi_log2 <= 2 ? tab2[lpi_log2] : tab[lpi_log2];
 }
 
 template <int PREC, bool EPS0, bool PHI = true>
-auto pick_kernel(int lpi_log2, int nw)
+auto pick_kernel(int lpi_log2, int nw, int ipt = 1)
 {
     if (nw == 1)
-        return pick_lpi<PREC, EPS0, 1, PHI>(lpi_log2);
+        return pick_lpi<PREC, EPS0, 1, PHI>(lpi_log2, ipt);
     if (nw == 2)
-        return pick_lpi<PREC, EPS0, 2, PHI>(lpi_log2);
-    return pick_lpi<PREC, EPS0, 4, PHI>(lpi_log2);
+        return pick_lpi<PREC, EPS0, 2, PHI>(lpi_log2, ipt);
+    return pick_lpi<PREC, EPS0, 4, PHI>(lpi_log2, ipt);
 }
 
 // the four (eps = 0, potential) variants of one precision
 template <int PREC>
-auto pick_variant(int lpi_log2, int nw, bool eps0, bool phi)
+auto pick_variant(int lpi_log2, int nw, int ipt, bool eps0, bool phi)
 {
     if (eps0)
-        return phi ? pick_kernel<PREC, true, true>(lpi_log2, nw)
-                   : pick_kernel<PREC, true, false>(lpi_log2, nw);
-    return phi ? pick_kernel<PREC, false, true>(lpi_log2, nw)
-               : pick_kernel<PREC, false, false>(lpi_log2, nw);
+        return phi ? pick_kernel<PREC, true, true>(lpi_log2, nw, ipt)
+                   : pick_kernel<PREC, true, false>(lpi_log2, nw, ipt);
+    return phi ? pick_kernel<PREC, false, true>(lpi_log2, nw, ipt)
+               : pick_kernel<PREC, false, false>(lpi_log2, nw, ipt);
 }
 
 int ilog2(int64_t v)
@@ -254,7 +263,7 @@ int ilog2(int64_t v)
 
 }  // namespace
 
-int64_t iblock_size(const Launch &L) { return (int64_t)L.waves * (64 / L.lpi); }
+int64_t iblock_size(const Launch &L) { return (int64_t)L.waves * (64 / L.lpi) * L.ipt; }
 
 // Launch shape: the pinned one, else the autotuner's for this power of two
 // of N_act, else a rule (below).
@@ -274,20 +283,30 @@ Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
             return L;
         }
     }
-    // Rule fitted to the autotuner's choices on 16,384- and 65,536-source
-    // spheres: 4 waves; about 4096 lanes per split (lanes per particle
-    // 4096 / N_act, between 1 and 64); then split the sources while every
-    // split keeps two tiles and the grid stays within 2^19 lanes.
+    return rule_launch(n_act, n_src, c.part_cap, c.cfg.precision);
+}
+
+// Rule fitted to the autotuner's choices on 16,384- and 65,536-source
+// spheres: 4 waves; about 4096 lanes per split (lanes per particle
+// 4096 / N_act, between 1 and 64); two particles per lane group for active
+// sets of 2^15 and more in the modes with FP64 pair arithmetic (it halves
+// the LDS reads per pair: 1-3 % faster there, measured; the FP32-pair mode
+// is faster with one); then split the sources while every split keeps two
+// tiles, the grid stays within 2^19 lanes and the partials (split x N_act
+// slots) fit part_cap.
+Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
+{
     Launch L;
     L.waves = 4;
     L.lpi = 1;
     L.split = 1;
     while (n_act * L.lpi < 4096 && L.lpi < 64)
         L.lpi <<= 1;
+    L.ipt = prec != NBODY_PREC_FP32PAIR && L.lpi <= 4 && n_act * L.lpi >= (int64_t(1) << 15) ? 2 : 1;
     const int64_t nt = 64 * L.waves;
     const int64_t max_lanes = int64_t(1) << 19;
-    while (n_act * L.lpi * L.split * 2 <= max_lanes && n_src / ((int64_t)L.split * 2) >= 2 * nt &&
-           (int64_t)L.split * 2 * n_act <= c.part_cap)
+    while (n_act * L.lpi / L.ipt * L.split * 2 <= max_lanes &&
+           n_src / ((int64_t)L.split * 2) >= 2 * nt && (int64_t)L.split * 2 * n_act <= part_cap)
         L.split <<= 1;
     return L;
 }
@@ -306,13 +325,14 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
     const int prec = c.cfg.precision;
     const bool phi = out.pot != nullptr;   // potential wanted (not in block steps)
     const int rec = prof_begin(c, PH_FORCE, n_act_total);
-    if (prec == NBODY_PREC_MIXED || prec == NBODY_PREC_FP32PAIR) {
-        const KMixed k = prec == NBODY_PREC_MIXED
-                             ? pick_variant<PREC_MIXED>(lg, L.waves, eps0, phi)
-                             : pick_variant<PREC_PAIR32>(lg, L.waves, eps0, phi);
+    if (prec == NBODY_PREC_MIXED) {
+        const KMixed k = pick_variant<PREC_MIXED>(lg, L.waves, L.ipt, eps0, phi);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jm, w, out, part, n_act_total, eps2);
+    } else if (prec == NBODY_PREC_FP32PAIR) {
+        const KPair32 k = pick_variant<PREC_PAIR32>(lg, L.waves, L.ipt, eps0, phi);
+        hipLaunchKernelGGL(k, grid, block, 0, s, c.jp, w, out, part, n_act_total, eps2);
     } else {
-        const KF64 k = pick_variant<PREC_F64>(lg, L.waves, eps0, phi);
+        const KF64 k = pick_variant<PREC_F64>(lg, L.waves, L.ipt, eps0, phi);
         hipLaunchKernelGGL(k, grid, block, 0, s, c.jd, w, out, part, n_act_total, eps2);
     }
     prof_end(c, rec);

@@ -35,7 +35,7 @@ struct Smem<PREC_MIXED> {
 };
 template <>
 struct Smem<PREC_PAIR32> {
-    using R = JRecMixed;
+    using R = JRecPair32;
 };
 template <>
 struct Smem<PREC_F64> {
@@ -75,30 +75,34 @@ __device__ __forceinline__ double rinv_f64(double r2)
 // the device-resident block-step loop calls it for the units it takes.
 // Every early return is uniform over the workgroup.  PHI: also sum the
 // potential (nbody_force, the start-up pass); a block step's evaluation
-// does not need it (the energy has its own pass).
-template <int PREC, int LPI, int NW, bool EPS0, bool PHI>
+// does not need it (the energy has its own pass).  IPT: active particles
+// per lane group (each source read from LDS serves IPT pairs).
+template <int PREC, int LPI, int NW, bool EPS0, bool PHI, int IPT = 1>
 __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, const ForceWork &w,
                                             const ForceOut &out, double *part,
                                             int64_t n_act_total, double eps2, int64_t g,
                                             int b)
 {
     constexpr int NT = NW * 64;      // sources per LDS tile
-    constexpr int GI = 64 / LPI;     // active particles per wave
-    constexpr int IB = NW * GI;      // active particles per workgroup
-    constexpr int PER = NT / LPI;    // pairs per lane per tile
+    constexpr int GI = 64 / LPI;     // lane groups (of LPI lanes) per wave
+    constexpr int NG = NW * GI;      // lane groups per workgroup
+    constexpr int IB = NG * IPT;     // active particles per workgroup
+    constexpr int PER = NT / LPI;    // sources per lane per tile
     constexpr bool MIXED = PREC == PREC_MIXED;
     constexpr bool P32 = PREC == PREC_PAIR32;
     constexpr bool INIT = PREC == PREC_INIT;
     constexpr int NV = INIT ? 12 : 9;   // vector outputs (3 components each)
-    // FP32 accumulators (mixed: jerk and snap; FP32-pair mode: all nine);
-    // FP64 ones for the rest
-    constexpr int NF = MIXED ? 6 : (P32 ? 9 : 1);
-    constexpr int ND = MIXED ? 3 : (P32 ? 1 : NV);
-    using VT = typename std::conditional<MIXED || P32, float, double>::type;
+    // FP32 accumulators (mixed: snap; FP32-pair mode: all nine); FP64 ones
+    // for the rest
+    constexpr int NF = MIXED ? 3 : (P32 ? 9 : 1);
+    constexpr int ND = MIXED ? 6 : (P32 ? 1 : NV);
+    // types of the sources' velocity and acceleration (as in the records)
+    using VV = typename std::conditional<P32, float, double>::type;
+    using VA = typename std::conditional<MIXED || P32, float, double>::type;
 
     __shared__ double s_x[NT], s_y[NT], s_z[NT], s_m[NT];
-    __shared__ VT s_vx[NT], s_vy[NT], s_vz[NT];
-    __shared__ VT s_ax[NT], s_ay[NT], s_az[NT];
+    __shared__ VV s_vx[NT], s_vy[NT], s_vz[NT];
+    __shared__ VA s_ax[NT], s_ay[NT], s_az[NT];
     __shared__ double s_jx[INIT ? NT : 1], s_jy[INIT ? NT : 1], s_jz[INIT ? NT : 1];
 
     // ---- which active slots and which sources this workgroup takes
@@ -124,35 +128,57 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int il = wave * GI + lane / LPI;
-    const int js = lane & (LPI - 1);
-    const int64_t k = kb + il;
-    const bool valid = k < s1;
-    const int64_t kk = valid ? k : kb;
-    const int64_t i = w.idx ? (int64_t)w.idx[kk] : kk;
-
-    const double xi = J.x[i], yi = J.y[i], zi = J.z[i];
-    const VT vxi = J.vx[i], vyi = J.vy[i], vzi = J.vz[i];
-    const VT axi = J.ax[i], ayi = J.ay[i], azi = J.az[i];
-    double jxi = 0, jyi = 0, jzi = 0;
-    if constexpr (INIT) {
-        jxi = J.jx[i]; jyi = J.jy[i]; jzi = J.jz[i];
+    const int il = wave * GI + lane / LPI;   // lane group
+    const int js = lane & (LPI - 1);         // slot within the group
+    // particle u of the lane group: active slot kb + il + u NG
+    int64_t k[IPT], i[IPT];
+    bool valid[IPT];
+    double xi[IPT], yi[IPT], zi[IPT];
+    VV vxi[IPT], vyi[IPT], vzi[IPT];
+    VA axi[IPT], ayi[IPT], azi[IPT];
+    double jxi[IPT], jyi[IPT], jzi[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        k[u] = kb + il + u * NG;
+        valid[u] = k[u] < s1;
+        const int64_t kk = valid[u] ? k[u] : kb;
+        i[u] = w.idx ? (int64_t)w.idx[kk] : kk;
+        if (i[u] < o0 || i[u] >= o1) {
+            // an index outside its cluster (a caller's bad list): skip the
+            // slot, load a valid particle, report
+            if (valid[u] && js == 0 && w.err)
+                atomicOr(w.err, ERR_BADIDX);
+            valid[u] = false;
+            i[u] = o0;
+        }
+        xi[u] = J.x[i[u]]; yi[u] = J.y[i[u]]; zi[u] = J.z[i[u]];
+        vxi[u] = J.vx[i[u]]; vyi[u] = J.vy[i[u]]; vzi[u] = J.vz[i[u]];
+        axi[u] = J.ax[i[u]]; ayi[u] = J.ay[i[u]]; azi[u] = J.az[i[u]];
+        jxi[u] = 0; jyi[u] = 0; jzi[u] = 0;
+        if constexpr (INIT) {
+            jxi[u] = J.jx[i[u]]; jyi[u] = J.jy[i[u]]; jzi[u] = J.jz[i[u]];
+        }
     }
 
-    // FP64 sums (mixed: acceleration; otherwise everything), the potential
-    // in FP64 always, and double-single (hi, lo) pairs for the mixed jerk
-    // and snap, fed by FP32 partial sums over at most FOLD pairs per lane
-    double D[ND];
+    // FP64 sums (mixed: acceleration and jerk; FP64 passes: everything),
+    // the potential in FP64 always, and double-single (hi, lo) pairs for
+    // the FP32 sums (mixed: snap; FP32-pair mode: everything), fed by FP32
+    // partial sums over at most FOLD pairs per lane
+    double D[IPT][ND];
+    float H[IPT][NF], L[IPT][NF];
+    double phi[IPT];
 #pragma unroll
-    for (int q = 0; q < ND; ++q)
-        D[q] = 0.0;
-    float H[NF], L[NF];
+    for (int u = 0; u < IPT; ++u) {
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        H[q] = 0.0f;
-        L[q] = 0.0f;
+        for (int q = 0; q < ND; ++q)
+            D[u][q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            H[u][q] = 0.0f;
+            L[u][q] = 0.0f;
+        }
+        phi[u] = 0.0;
     }
-    double phi = 0.0;
 
     for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
@@ -181,205 +207,228 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
         __syncthreads();
 
         // a short FP32 partial keeps its rounding small (64 pairs measured
-        // 3x better than 256 for the jerk, at ~1% more instructions)
+        // 3x better than 256 for FP32 jerk sums, at ~1% more instructions)
         constexpr int FOLD = (MIXED || P32) ? (PER < 64 ? PER : 64) : PER;
         for (int p0 = 0; p0 < PER; p0 += FOLD) {
-            float T[NF];
+            float T[IPT][NF];
 #pragma unroll
-            for (int q = 0; q < NF; ++q)
-                T[q] = 0.0f;
+            for (int u = 0; u < IPT; ++u)
+#pragma unroll
+                for (int q = 0; q < NF; ++q)
+                    T[u][q] = 0.0f;
 
-#pragma unroll 4
+            constexpr int UNROLL = IPT == 1 ? 4 : 2;
+#pragma unroll UNROLL
             for (int p = p0; p < p0 + FOLD; ++p) {
                 const int t = js + p * LPI;
-                if constexpr (P32) {
-                    // every pair term in FP32 from the FP64 difference r_j - r_i
-                    const float dx = (float)(s_x[t] - xi), dy = (float)(s_y[t] - yi),
-                                dz = (float)(s_z[t] - zi);
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)eps2)));
-                    float rinv = __builtin_amdgcn_rsqf(r2);
+                const double sx = s_x[t], sy = s_y[t], sz = s_z[t], sm = s_m[t];
+                const VV svx = s_vx[t], svy = s_vy[t], svz = s_vz[t];
+                const VA sax = s_ax[t], say = s_ay[t], saz = s_az[t];
+#pragma unroll
+                for (int u = 0; u < IPT; ++u) {
+                    if constexpr (P32) {
+                        // every pair term in FP32 from the FP64 difference r_j - r_i
+                        const float dx = (float)(sx - xi[u]), dy = (float)(sy - yi[u]),
+                                    dz = (float)(sz - zi[u]);
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)eps2)));
+                        float rinv = __builtin_amdgcn_rsqf(r2);
+                        if constexpr (EPS0)
+                            rinv = r2 > 0.0f ? rinv : 0.0f;
+                        const float mrinv = (float)sm * rinv;
+                        if constexpr (PHI)
+                            phi[u] -= (double)mrinv;
+                        const float rinv2 = rinv * rinv, mr3 = mrinv * rinv2;
+                        const float dvx = svx - vxi[u], dvy = svy - vyi[u], dvz = svz - vzi[u];
+                        const float dax = sax - axi[u], day = say - ayi[u], daz = saz - azi[u];
+                        const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+                        const float qq = fmaf(dvx, dvx, fmaf(dvy, dvy, fmaf(dvz, dvz,
+                                         fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
+                        const float alpha = rv * rinv2;
+                        const float beta = fmaf(alpha, alpha, qq * rinv2);
+                        const float a3 = -3.0f * alpha, a6 = a3 + a3, b3 = -3.0f * beta;
+                        const float jx = fmaf(a3, dx, dvx), jy = fmaf(a3, dy, dvy),
+                                    jz = fmaf(a3, dz, dvz);
+                        float *Tu = T[u];
+                        Tu[0] = fmaf(mr3, dx, Tu[0]);
+                        Tu[1] = fmaf(mr3, dy, Tu[1]);
+                        Tu[2] = fmaf(mr3, dz, Tu[2]);
+                        Tu[3] = fmaf(mr3, jx, Tu[3]);
+                        Tu[4] = fmaf(mr3, jy, Tu[4]);
+                        Tu[5] = fmaf(mr3, jz, Tu[5]);
+                        Tu[6] = fmaf(mr3, fmaf(a6, jx, fmaf(b3, dx, dax)), Tu[6]);
+                        Tu[7] = fmaf(mr3, fmaf(a6, jy, fmaf(b3, dy, day)), Tu[7]);
+                        Tu[8] = fmaf(mr3, fmaf(a6, jz, fmaf(b3, dz, daz)), Tu[8]);
+                        continue;
+                    }
+                    const double dxd = sx - xi[u], dyd = sy - yi[u], dzd = sz - zi[u];
+                    const double r2 = fma(dxd, dxd, fma(dyd, dyd, fma(dzd, dzd, eps2)));
+                    double rinv;
+                    if constexpr (MIXED)
+                        rinv = rinv_mixed(r2);
+                    else
+                        rinv = rinv_f64(r2);
                     if constexpr (EPS0)
-                        rinv = r2 > 0.0f ? rinv : 0.0f;
-                    const float mrinv = (float)s_m[t] * rinv;
+                        rinv = r2 > 0.0 ? rinv : 0.0;
+                    const double mrinv = sm * rinv;
                     if constexpr (PHI)
-                        phi -= (double)mrinv;
-                    const float rinv2 = rinv * rinv, mr3 = mrinv * rinv2;
-                    const float dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
-                    const float dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
-                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-                    const float qq = fmaf(dvx, dvx, fmaf(dvy, dvy, fmaf(dvz, dvz,
-                                     fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
-                    const float alpha = rv * rinv2;
-                    const float beta = fmaf(alpha, alpha, qq * rinv2);
-                    const float a3 = -3.0f * alpha, a6 = a3 + a3, b3 = -3.0f * beta;
-                    const float jx = fmaf(a3, dx, dvx), jy = fmaf(a3, dy, dvy), jz = fmaf(a3, dz, dvz);
-                    T[0] = fmaf(mr3, dx, T[0]);
-                    T[1] = fmaf(mr3, dy, T[1]);
-                    T[2] = fmaf(mr3, dz, T[2]);
-                    T[3] = fmaf(mr3, jx, T[3]);
-                    T[4] = fmaf(mr3, jy, T[4]);
-                    T[5] = fmaf(mr3, jz, T[5]);
-                    T[6] = fmaf(mr3, fmaf(a6, jx, fmaf(b3, dx, dax)), T[6]);
-                    T[7] = fmaf(mr3, fmaf(a6, jy, fmaf(b3, dy, day)), T[7]);
-                    T[8] = fmaf(mr3, fmaf(a6, jz, fmaf(b3, dz, daz)), T[8]);
-                    continue;
-                }
-                const double dxd = s_x[t] - xi, dyd = s_y[t] - yi, dzd = s_z[t] - zi;
-                const double r2 = fma(dxd, dxd, fma(dyd, dyd, fma(dzd, dzd, eps2)));
-                double rinv;
-                if constexpr (MIXED)
-                    rinv = rinv_mixed(r2);
-                else
-                    rinv = rinv_f64(r2);
-                if constexpr (EPS0)
-                    rinv = r2 > 0.0 ? rinv : 0.0;
-                const double mrinv = s_m[t] * rinv;
-                if constexpr (PHI)
-                    phi -= mrinv;
-                const double rinv2 = rinv * rinv;
-                const double mr3 = mrinv * rinv2;
-                if constexpr (MIXED) {
-                    // acceleration in FP64; jerk and snap in FP32:
-                    // J = m r^-3 (v - 3 alpha r), S = m r^-3 (a - 6 alpha jv - 3 beta r)
-                    D[0] = fma(mr3, dxd, D[0]);
-                    D[1] = fma(mr3, dyd, D[1]);
-                    D[2] = fma(mr3, dzd, D[2]);
-                    const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-                    const float fr2 = (float)rinv2, fm3 = (float)mr3;
-                    const float dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
-                    const float dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
-                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-                    const float qq = fmaf(dvx, dvx, fmaf(dvy, dvy, fmaf(dvz, dvz,
-                                     fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
-                    const float alpha = rv * fr2;
-                    const float beta = fmaf(alpha, alpha, qq * fr2);
-                    const float a3 = -3.0f * alpha;
-                    const float a6 = a3 + a3;
-                    const float b3 = -3.0f * beta;
-                    const float jx = fmaf(a3, dx, dvx), jy = fmaf(a3, dy, dvy), jz = fmaf(a3, dz, dvz);
-                    const float sx = fmaf(a6, jx, fmaf(b3, dx, dax));
-                    const float sy = fmaf(a6, jy, fmaf(b3, dy, day));
-                    const float sz = fmaf(a6, jz, fmaf(b3, dz, daz));
-                    T[0] = fmaf(fm3, jx, T[0]);
-                    T[1] = fmaf(fm3, jy, T[1]);
-                    T[2] = fmaf(fm3, jz, T[2]);
-                    T[3] = fmaf(fm3, sx, T[3]);
-                    T[4] = fmaf(fm3, sy, T[4]);
-                    T[5] = fmaf(fm3, sz, T[5]);
-                } else {
-                    const double dvx = s_vx[t] - vxi, dvy = s_vy[t] - vyi, dvz = s_vz[t] - vzi;
-                    const double dax = s_ax[t] - axi, day = s_ay[t] - ayi, daz = s_az[t] - azi;
-                    const double alpha = fma(dxd, dvx, fma(dyd, dvy, dzd * dvz)) * rinv2;
-                    const double qq = fma(dvx, dvx, fma(dvy, dvy, fma(dvz, dvz,
-                                      fma(dxd, dax, fma(dyd, day, dzd * daz)))));
-                    const double beta = fma(alpha, alpha, qq * rinv2);
-                    if constexpr (INIT) {
-                        // start-up evaluation with the crackle, term by term
-                        const double djx = s_jx[t] - jxi, djy = s_jy[t] - jyi, djz = s_jz[t] - jzi;
-                        const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) +
-                                              dxd * djx + dyd * djy + dzd * djz) * rinv2 +
-                                             alpha * (3.0 * beta - 4.0 * alpha * alpha);
-                        const double Ax = mr3 * dxd, Ay = mr3 * dyd, Az = mr3 * dzd;
-                        const double Jx = mr3 * dvx - 3.0 * alpha * Ax;
-                        const double Jy = mr3 * dvy - 3.0 * alpha * Ay;
-                        const double Jz = mr3 * dvz - 3.0 * alpha * Az;
-                        const double Sx = mr3 * dax - 6.0 * alpha * Jx - 3.0 * beta * Ax;
-                        const double Sy = mr3 * day - 6.0 * alpha * Jy - 3.0 * beta * Ay;
-                        const double Sz = mr3 * daz - 6.0 * alpha * Jz - 3.0 * beta * Az;
-                        D[0] += Ax; D[1] += Ay; D[2] += Az;
-                        D[3] += Jx; D[4] += Jy; D[5] += Jz;
-                        D[6] += Sx; D[7] += Sy; D[8] += Sz;
-                        D[ND - 3] += mr3 * djx - 9.0 * alpha * Sx - 9.0 * beta * Jx - 3.0 * gamma * Ax;
-                        D[ND - 2] += mr3 * djy - 9.0 * alpha * Sy - 9.0 * beta * Jy - 3.0 * gamma * Ay;
-                        D[ND - 1] += mr3 * djz - 9.0 * alpha * Sz - 9.0 * beta * Jz - 3.0 * gamma * Az;
+                        phi[u] -= mrinv;
+                    const double rinv2 = rinv * rinv;
+                    const double mr3 = mrinv * rinv2;
+                    double *Du = D[u];
+                    if constexpr (MIXED) {
+                        // acceleration and jerk in FP64, snap in FP32:
+                        // A = m r^-3 r, J = m r^-3 (v - 3 alpha r),
+                        // S = m r^-3 (a - 6 alpha jv - 3 beta r), jv = v - 3 alpha r
+                        Du[0] = fma(mr3, dxd, Du[0]);
+                        Du[1] = fma(mr3, dyd, Du[1]);
+                        Du[2] = fma(mr3, dzd, Du[2]);
+                        const double dvx = svx - vxi[u], dvy = svy - vyi[u], dvz = svz - vzi[u];
+                        const double m3r2 = -3.0 * rinv2;
+                        const double a3d = fma(dxd, dvx, fma(dyd, dvy, dzd * dvz)) * m3r2;  // -3 alpha
+                        const double jxd = fma(a3d, dxd, dvx), jyd = fma(a3d, dyd, dvy),
+                                     jzd = fma(a3d, dzd, dvz);
+                        Du[3] = fma(mr3, jxd, Du[3]);
+                        Du[4] = fma(mr3, jyd, Du[4]);
+                        Du[5] = fma(mr3, jzd, Du[5]);
+                        const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                        const float fvx = (float)dvx, fvy = (float)dvy, fvz = (float)dvz;
+                        const float jx = (float)jxd, jy = (float)jyd, jz = (float)jzd;
+                        const float a3 = (float)a3d, f3r2 = (float)m3r2, fm3 = (float)mr3;
+                        const float dax = sax - axi[u], day = say - ayi[u], daz = saz - azi[u];
+                        const float qq = fmaf(fvx, fvx, fmaf(fvy, fvy, fmaf(fvz, fvz,
+                                         fmaf(dx, dax, fmaf(dy, day, dz * daz)))));
+                        // -3 beta = -3 alpha^2 - 3 qq / s^2, with alpha = -a3 / 3
+                        const float b3 = fmaf(a3, a3 * (-1.0f / 3.0f), qq * f3r2);
+                        const float a6 = a3 + a3;
+                        const float sxf = fmaf(a6, jx, fmaf(b3, dx, dax));
+                        const float syf = fmaf(a6, jy, fmaf(b3, dy, day));
+                        const float szf = fmaf(a6, jz, fmaf(b3, dz, daz));
+                        T[u][0] = fmaf(fm3, sxf, T[u][0]);
+                        T[u][1] = fmaf(fm3, syf, T[u][1]);
+                        T[u][2] = fmaf(fm3, szf, T[u][2]);
                     } else {
-                        const double a3 = -3.0 * alpha, a6 = a3 + a3, b3 = -3.0 * beta;
-                        const double jx = fma(a3, dxd, dvx), jy = fma(a3, dyd, dvy), jz = fma(a3, dzd, dvz);
-                        D[0] = fma(mr3, dxd, D[0]);
-                        D[1] = fma(mr3, dyd, D[1]);
-                        D[2] = fma(mr3, dzd, D[2]);
-                        D[3] = fma(mr3, jx, D[3]);
-                        D[4] = fma(mr3, jy, D[4]);
-                        D[5] = fma(mr3, jz, D[5]);
-                        D[6] = fma(mr3, fma(a6, jx, fma(b3, dxd, dax)), D[6]);
-                        D[7] = fma(mr3, fma(a6, jy, fma(b3, dyd, day)), D[7]);
-                        D[8] = fma(mr3, fma(a6, jz, fma(b3, dzd, daz)), D[8]);
+                        const double dvx = svx - vxi[u], dvy = svy - vyi[u], dvz = svz - vzi[u];
+                        const double dax = sax - axi[u], day = say - ayi[u], daz = saz - azi[u];
+                        const double alpha = fma(dxd, dvx, fma(dyd, dvy, dzd * dvz)) * rinv2;
+                        const double qq = fma(dvx, dvx, fma(dvy, dvy, fma(dvz, dvz,
+                                          fma(dxd, dax, fma(dyd, day, dzd * daz)))));
+                        const double beta = fma(alpha, alpha, qq * rinv2);
+                        if constexpr (INIT) {
+                            // start-up evaluation with the crackle, term by term
+                            const double djx = s_jx[t] - jxi[u], djy = s_jy[t] - jyi[u],
+                                         djz = s_jz[t] - jzi[u];
+                            const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) +
+                                                  dxd * djx + dyd * djy + dzd * djz) * rinv2 +
+                                                 alpha * (3.0 * beta - 4.0 * alpha * alpha);
+                            const double Ax = mr3 * dxd, Ay = mr3 * dyd, Az = mr3 * dzd;
+                            const double Jx = mr3 * dvx - 3.0 * alpha * Ax;
+                            const double Jy = mr3 * dvy - 3.0 * alpha * Ay;
+                            const double Jz = mr3 * dvz - 3.0 * alpha * Az;
+                            const double Sx = mr3 * dax - 6.0 * alpha * Jx - 3.0 * beta * Ax;
+                            const double Sy = mr3 * day - 6.0 * alpha * Jy - 3.0 * beta * Ay;
+                            const double Sz = mr3 * daz - 6.0 * alpha * Jz - 3.0 * beta * Az;
+                            Du[0] += Ax; Du[1] += Ay; Du[2] += Az;
+                            Du[3] += Jx; Du[4] += Jy; Du[5] += Jz;
+                            Du[6] += Sx; Du[7] += Sy; Du[8] += Sz;
+                            Du[ND - 3] += mr3 * djx - 9.0 * alpha * Sx - 9.0 * beta * Jx - 3.0 * gamma * Ax;
+                            Du[ND - 2] += mr3 * djy - 9.0 * alpha * Sy - 9.0 * beta * Jy - 3.0 * gamma * Ay;
+                            Du[ND - 1] += mr3 * djz - 9.0 * alpha * Sz - 9.0 * beta * Jz - 3.0 * gamma * Az;
+                        } else {
+                            const double a3 = -3.0 * alpha, a6 = a3 + a3, b3 = -3.0 * beta;
+                            const double jx = fma(a3, dxd, dvx), jy = fma(a3, dyd, dvy),
+                                         jz = fma(a3, dzd, dvz);
+                            Du[0] = fma(mr3, dxd, Du[0]);
+                            Du[1] = fma(mr3, dyd, Du[1]);
+                            Du[2] = fma(mr3, dzd, Du[2]);
+                            Du[3] = fma(mr3, jx, Du[3]);
+                            Du[4] = fma(mr3, jy, Du[4]);
+                            Du[5] = fma(mr3, jz, Du[5]);
+                            Du[6] = fma(mr3, fma(a6, jx, fma(b3, dxd, dax)), Du[6]);
+                            Du[7] = fma(mr3, fma(a6, jy, fma(b3, dyd, day)), Du[7]);
+                            Du[8] = fma(mr3, fma(a6, jz, fma(b3, dzd, daz)), Du[8]);
+                        }
                     }
                 }
             }
             if constexpr (MIXED || P32) {
 #pragma unroll
-                for (int q = 0; q < NF; ++q)
-                    ds_add(H[q], L[q], T[q]);
+                for (int u = 0; u < IPT; ++u)
+#pragma unroll
+                    for (int q = 0; q < NF; ++q)
+                        ds_add(H[u][q], L[u][q], T[u][q]);
             }
         }
     }
 
-    // ---- combine the LPI lanes of each active particle (xor butterfly)
-    double R[NV + 1];
-    if constexpr (P32) {
 #pragma unroll
-        for (int q = 0; q < NF; ++q)
-            R[q] = (double)H[q] + (double)L[q];
-    } else if constexpr (MIXED) {
+    for (int u = 0; u < IPT; ++u) {
+        // ---- combine the LPI lanes of each active particle (xor butterfly)
+        double R[NV + 1];
+        if constexpr (P32) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-            R[q] = D[q];
+            for (int q = 0; q < NF; ++q)
+                R[q] = (double)H[u][q] + (double)L[u][q];
+        } else if constexpr (MIXED) {
 #pragma unroll
-        for (int q = 0; q < NF; ++q)
-            R[3 + q] = (double)H[q] + (double)L[q];
-    } else {
+            for (int q = 0; q < 6; ++q)
+                R[q] = D[u][q];
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            R[q] = D[q];
-    }
-    R[NV] = phi;
+            for (int q = 0; q < NF; ++q)
+                R[6 + q] = (double)H[u][q] + (double)L[u][q];
+        } else {
 #pragma unroll
-    for (int msk = 1; msk < LPI; msk <<= 1) {
+            for (int q = 0; q < NV; ++q)
+                R[q] = D[u][q];
+        }
+        R[NV] = phi[u];
 #pragma unroll
-        for (int q = 0; q < NV + 1; ++q)
-            R[q] += __shfl_xor(R[q], msk, 64);
-    }
+        for (int msk = 1; msk < LPI; msk <<= 1) {
+#pragma unroll
+            for (int q = 0; q < NV + 1; ++q)
+                R[q] += __shfl_xor(R[q], msk, 64);
+        }
 
-    if (!valid || js != 0)
-        return;
-    // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
-    // potential: remove that term, computed with the same operations
-    if constexpr (!EPS0 && PHI) {
-        if (i >= j0 && i < j1) {
-            if constexpr (P32) {
-                const float e2f = (float)eps2;
-                const float ri = __builtin_amdgcn_rsqf(fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, e2f))));
-                R[NV] += (double)((float)J.m[i] * ri);
-            } else {
-                const double r2 = fma(0.0, 0.0, fma(0.0, 0.0, fma(0.0, 0.0, eps2)));
-                const double ri = MIXED ? rinv_mixed(r2) : rinv_f64(r2);
-                R[NV] += J.m[i] * ri;
+        if (!valid[u] || js != 0)
+            continue;
+        const int64_t ku = k[u], iu = i[u];
+        // the j == i pair adds exactly zero to a, da, d2a but -m_i / eps to the
+        // potential: remove that term, computed with the same operations
+        if constexpr (!EPS0 && PHI) {
+            if (iu >= j0 && iu < j1) {
+                if constexpr (P32) {
+                    const float e2f = (float)eps2;
+                    const float ri = __builtin_amdgcn_rsqf(fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, fmaf(0.0f, 0.0f, e2f))));
+                    R[NV] += (double)((float)J.m[iu] * ri);
+                } else {
+                    const double r2 = fma(0.0, 0.0, fma(0.0, 0.0, fma(0.0, 0.0, eps2)));
+                    const double ri = MIXED ? rinv_mixed(r2) : rinv_f64(r2);
+                    R[NV] += J.m[iu] * ri;
+                }
             }
         }
-    }
-    if constexpr (INIT) {
+        if constexpr (INIT) {
 #pragma unroll
-        for (int q = 0; q < NV / 3; ++q)
-            if (out.vec[q])
+            for (int q = 0; q < NV / 3; ++q)
+                if (out.vec[q])
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        out.vec[q][ku * out.sk + d * out.sd] = R[3 * q + d];
+            continue;
+        }
+        if (part) {
+            double *pb = part + (int64_t)b * 10 * n_act_total + ku;
+#pragma unroll
+            for (int q = 0; q < 10; ++q)
+                pb[(int64_t)q * n_act_total] = R[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
-        return;
-    }
-    if (part) {
-        double *pb = part + (int64_t)b * 10 * n_act_total + k;
-#pragma unroll
-        for (int q = 0; q < 10; ++q)
-            pb[(int64_t)q * n_act_total] = R[q];
-    } else {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                out.vec[q][k * out.sk + d * out.sd] = R[3 * q + d];
-        if (out.pot)
-            out.pot[k] = R[NV];
+                    out.vec[q][ku * out.sk + d * out.sd] = R[3 * q + d];
+            if (out.pot)
+                out.pot[ku] = R[NV];
+        }
     }
 }
 

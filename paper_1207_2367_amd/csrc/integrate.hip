@@ -70,11 +70,13 @@ __device__ uint32_t block_dt(double crit, double dt_old, double t_new, double t_
 // Taylor series of paper Sect. 3 item 1 (Horner form) to the source
 // records.  T is the block time of the particle's cluster, or its own time
 // (h = 0: the records are the stored state) when own_time is set.
-__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, const JRecF64 &jd,
-                                       int prec, int64_t n, int64_t i, double h);
+__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm,
+                                       const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                       int64_t n, int64_t i, double h);
 
 __device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
-                                         const JRecF64 &jd, int prec, int64_t n,
+                                         const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                         int64_t n,
                                          const double *Tc, const int32_t *cluster_of,
                                          int own_time, int64_t i)
 {
@@ -87,12 +89,13 @@ __device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
             return;  // cluster has reached the target: not a source this step
         h = T - st.t[i];
     }
-    pack_h(st, jm, jd, prec, n, i, h);
+    pack_h(st, jm, jp, jd, prec, n, i, h);
 }
 
 // the records of particle i advanced by h from its own time
-__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, const JRecF64 &jd,
-                                       int prec, int64_t n, int64_t i, double h)
+__device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm,
+                                       const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                       int64_t n, int64_t i, double h)
 {
     double xp[3], vp[3], ap[3];
 #pragma unroll
@@ -105,11 +108,16 @@ __device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, con
         ap[d] = a + h * (j + h * (s * 0.5 + h * (c * (1.0 / 6))));
     }
     const double m = st.mass[i];
-    if (prec != NBODY_PREC_FP64) {
+    if (prec == NBODY_PREC_MIXED) {
         jm.x[i] = xp[0]; jm.y[i] = xp[1]; jm.z[i] = xp[2];
-        jm.vx[i] = (float)vp[0]; jm.vy[i] = (float)vp[1]; jm.vz[i] = (float)vp[2];
+        jm.vx[i] = vp[0]; jm.vy[i] = vp[1]; jm.vz[i] = vp[2];
         jm.ax[i] = (float)ap[0]; jm.ay[i] = (float)ap[1]; jm.az[i] = (float)ap[2];
         jm.m[i] = m;
+    } else if (prec == NBODY_PREC_FP32PAIR) {
+        jp.x[i] = xp[0]; jp.y[i] = xp[1]; jp.z[i] = xp[2];
+        jp.vx[i] = (float)vp[0]; jp.vy[i] = (float)vp[1]; jp.vz[i] = (float)vp[2];
+        jp.ax[i] = (float)ap[0]; jp.ay[i] = (float)ap[1]; jp.az[i] = (float)ap[2];
+        jp.m[i] = m;
     } else {
         jd.x[i] = xp[0]; jd.y[i] = xp[1]; jd.z[i] = xp[2];
         jd.vx[i] = vp[0]; jd.vy[i] = vp[1]; jd.vz[i] = vp[2];
@@ -118,11 +126,11 @@ __device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm, con
     }
 }
 
-__global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecF64 jd,
+__global__ __launch_bounds__(TPB) void pack_kernel(State st, JRecMixed jm, JRecPair32 jp, JRecF64 jd,
                                                    int prec, int64_t n, const double *Tc,
                                                    const int32_t *cluster_of, int own_time)
 {
-    pack_one(st, jm, jd, prec, n, Tc, cluster_of, own_time,
+    pack_one(st, jm, jp, jd, prec, n, Tc, cluster_of, own_time,
              (int64_t)blockIdx.x * TPB + threadIdx.x);
 }
 
@@ -421,7 +429,7 @@ __global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const doub
 // workgroups compact one chunk each, the rest predict TPB sources each to
 // their cluster's block time.  Both read only the schedule's results and
 // the stored state; they write disjoint arrays.
-__global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed jm, JRecF64 jd,
+__global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed jm, JRecPair32 jp, JRecF64 jd,
                                                            int prec, int64_t n,
                                                            const int32_t *cluster_of,
                                                            const int64_t *chunk_begin,
@@ -434,7 +442,7 @@ __global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed j
         scatter_chunk(st.t, st.dt, chunk_begin, chunk_cluster, tblock, chunk_pos, act,
                       blockIdx.x);
     else
-        pack_one(st, jm, jd, prec, n, tblock, cluster_of, 0,
+        pack_one(st, jm, jp, jd, prec, n, tblock, cluster_of, 0,
                  ((int64_t)blockIdx.x - n_chunks) * TPB + threadIdx.x);
 }
 
@@ -633,6 +641,11 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
     const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (k >= n_act)
         return;
+    const int32_t i = idx[k];
+    if (i < 0 || i >= n) {   // a caller's list out of range: report, touch nothing
+        atomicOr(err, ERR_BADIDX);
+        return;
+    }
     double a1[3], j1[3], s1[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -640,7 +653,7 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
         j1[d] = fj[k * sk + d * sd];
         s1[d] = fs[k * sk + d * sd];
     }
-    correct_one(st, n, idx[k], a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+    correct_one(st, n, i, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
 }
 
 // Split-source reduction and corrector of a block step in one kernel: a
@@ -830,10 +843,13 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v)
 
 template <int PREC>
 __device__ __forceinline__ const typename Smem<PREC>::R &loop_records(const JRecMixed &jm,
+                                                                      const JRecPair32 &jp,
                                                                       const JRecF64 &jd)
 {
     if constexpr (std::is_same<typename Smem<PREC>::R, JRecMixed>::value)
         return jm;
+    else if constexpr (std::is_same<typename Smem<PREC>::R, JRecPair32>::value)
+        return jp;
     else
         return jd;
 }
@@ -843,13 +859,14 @@ __device__ __forceinline__ const typename Smem<PREC>::R &loop_records(const JRec
 // block it stopped at, then [7] = seq with system-scope release order.
 template <int PREC, bool EPS0>
 __global__ __launch_bounds__(TPB) void step_loop_kernel(
-    State st, JRecMixed jm, JRecF64 jd, int prec, int64_t n, double eps2, double t_target,
+    State st, JRecMixed jm, JRecPair32 jp, JRecF64 jd, int prec, int64_t n, double eps2,
+    double t_target,
     double eta, double dt_min, double dt_max, int64_t a_max, int32_t *act, double *part,
     int64_t *seg, const int64_t *off, uint64_t *wmin, int32_t *wcnt, uint32_t *bar,
     uint32_t *err, int64_t *hist, int64_t *res, int64_t seq)
 {
     __shared__ double sum[9][RC_SLOTS];
-    const auto &J = loop_records<PREC>(jm, jd);
+    const auto &J = loop_records<PREC>(jm, jp, jd);
     const uint32_t G = gridDim.x;
     const int64_t P = (n + G - 1) / G;
     const int64_t r0 = (int64_t)blockIdx.x * P < n ? (int64_t)blockIdx.x * P : n;
@@ -900,7 +917,7 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
         if (mine > 0)
             scatter_range(st.t, st.dt, T, r0, r1, first, act);
         for (int64_t i = r0 + threadIdx.x; i < r1; i += TPB)
-            pack_h(st, jm, jd, prec, n, i, T - st.t[i]);
+            pack_h(st, jm, jp, jd, prec, n, i, T - st.t[i]);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             seg[0] = 0;
             seg[1] = n_act;
@@ -1087,6 +1104,19 @@ __global__ void validate_idx_kernel(const int32_t *idx, int64_t n_act, int64_t n
         atomicOr(err, ERR_BADIDX);
 }
 
+// Energy precondition: every particle of a cluster at the cluster's first
+// particle's time (the sums of paper Sect. 5.1 are taken at a common time).
+__global__ void sync_check_kernel(const double *t, int64_t n, const int32_t *cluster_of,
+                                  const int64_t *off, uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int c = cluster_of ? cluster_of[i] : 0;
+    if (t[i] != t[off[c]])
+        atomicOr(err, ERR_STATE);
+}
+
 __global__ void aos_to_soa_kernel(const double *src, double *dst, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1126,7 +1156,7 @@ unsigned nblk(int64_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
 hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
                        const int32_t *cluster_of, hipStream_t s)
 {
-    hipLaunchKernelGGL(pack_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.jm, c.jd,
+    hipLaunchKernelGGL(pack_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, c.st, c.jm, c.jp, c.jd,
                        (int)c.cfg.precision, c.n, T_cluster, cluster_of, own_time);
     return hipGetLastError();
 }
@@ -1165,7 +1195,7 @@ hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStre
 hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s)
 {
     const unsigned nb = (unsigned)c.n_chunks + nblk(c.n);
-    hipLaunchKernelGGL(scatter_pack_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.jm, c.jd,
+    hipLaunchKernelGGL(scatter_pack_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.jm, c.jp, c.jd,
                        (int)c.cfg.precision, c.n, (const int32_t *)c.d_cluster_of,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
                        (const double *)c.d_tblock, (const int64_t *)c.d_chunk_pos, c.act,
@@ -1232,6 +1262,7 @@ hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int gr
 {
     State st = c.st;
     JRecMixed jm = c.jm;
+    JRecPair32 jp = c.jp;
     JRecF64 jd = c.jd;
     int prec = c.cfg.precision;
     int64_t n = c.n;
@@ -1248,7 +1279,7 @@ hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int gr
     uint32_t *err = c.d_err;
     int64_t *hist = c.d_info + 8;
     int64_t *res = c.d_tot + 8;
-    void *args[] = {&st,   &jm,  &jd,   &prec, &n,    &eps2, &tt,  &eta,  &dmin, &dmax, &am,
+    void *args[] = {&st,   &jm,  &jp,  &jd,   &prec, &n,    &eps2, &tt,  &eta,  &dmin, &dmax, &am,
                     &act,  &part, &seg, &off,  &wmin, &wcnt, &bar, &err,  &hist, &res,  &sq};
     return hipLaunchCooperativeKernel(step_loop_fn(c), dim3((unsigned)grid), dim3(TPB), args, 0,
                                       s);
@@ -1326,6 +1357,14 @@ hipError_t launch_validate_idx(const Ctx &c, int64_t n_act, const int32_t *idx, 
         return hipSuccess;
     hipLaunchKernelGGL(validate_idx_kernel, dim3(nblk(n_act)), dim3(TPB), 0, s, idx, n_act,
                        c.n, c.d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sync_check(const Ctx &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(sync_check_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s,
+                       (const double *)c.st.t, c.n, (const int32_t *)c.d_cluster_of,
+                       (const int64_t *)c.d_off, c.d_err);
     return hipGetLastError();
 }
 

@@ -15,13 +15,20 @@ namespace nb {
 // ---------------------------------------------------------------- records
 // Source ("j") records: the predicted state of every particle at the block
 // time, structure-of-arrays so that a tile load is coalesced.
-//   mixed: x, y, z and mass in FP64 (they enter the FP64 acceleration and
-//          potential), velocity and acceleration in FP32 -> 56 bytes
-//   fp64 : every field FP64                       -> 80 bytes per particle
-struct JRecMixed {
+//   mixed    : x, y, z, mass and velocity in FP64 (they enter the FP64
+//              acceleration, jerk and potential), acceleration in FP32
+//              (it enters only the FP32 snap)          -> 68 bytes
+//   FP32 pair: x, y, z and mass in FP64, velocity and acceleration in
+//              FP32                                    -> 56 bytes
+//   fp64     : every field FP64                        -> 80 bytes per particle
+template <typename VT>
+struct JRecMix {
     double *x, *y, *z, *m;
-    float *vx, *vy, *vz, *ax, *ay, *az;
+    VT *vx, *vy, *vz;
+    float *ax, *ay, *az;
 };
+using JRecMixed = JRecMix<double>;
+using JRecPair32 = JRecMix<float>;
 struct JRecF64 {
     double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *m;
     double *jx, *jy, *jz;   // sources' jerks: start-up evaluation only
@@ -58,10 +65,16 @@ struct ForceWork {
     int64_t n_blocks;         // i-blocks in the grid (x dimension)
     int32_t split;            // B, the split-source factor (grid y)
     int32_t nc;
+    // error word for an active particle outside its cluster's sources (a
+    // caller's bad index list; the slot is skipped), or nullptr
+    uint32_t *err;
 };
 
+// Launch shape of the evaluation: lanes per active particle, waves per
+// workgroup, split-source factor, active particles per lane group (1 or 2;
+// 2 only with lpi <= 4).
 struct Launch {
-    int lpi = 0, waves = 0, split = 0;
+    int lpi = 0, waves = 0, split = 0, ipt = 1;
 };
 
 // Sources per split of a cluster of nsrc sources under split factor B with
@@ -88,6 +101,7 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
 hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, int nt,
                                  int64_t n_act, double t_target, hipStream_t s);
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
+Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec);
 // start-up evaluation (FP64, a, da, d2a and crackle of every particle from
 // the stored state): split = 1, results written straight to out
 hipError_t launch_energy_pot(Ctx &c, double *phi, hipStream_t s);
@@ -120,6 +134,8 @@ hipError_t launch_energy_sums(const Ctx &c, const double *phi, double *out5,
                               hipStream_t s);
 hipError_t launch_validate_idx(const Ctx &c, int64_t n_act, const int32_t *idx,
                                hipStream_t s);
+// ERR_STATE unless every cluster's particles share one time
+hipError_t launch_sync_check(const Ctx &c, hipStream_t s);
 hipError_t launch_aos_to_soa(const double *src, double *dst, int64_t n,
                              hipStream_t s);
 hipError_t launch_soa_to_aos(const double *src, double *dst, int64_t n,
@@ -128,7 +144,9 @@ hipError_t launch_check_finite(const Ctx &c, hipStream_t s);
 hipError_t launch_init_dt(const Ctx &c, hipStream_t s);
 
 // Device error word bits (set with atomicOr by kernels).
-enum : uint32_t { ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u, ERR_LOOP = 8u };
+enum : uint32_t {
+    ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u, ERR_LOOP = 8u, ERR_STATE = 16u
+};
 
 // Device-resident block-step loop: why it stopped, and the largest grid.
 enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
@@ -159,6 +177,7 @@ struct Ctx {
     int device = 0;
     State st{};
     JRecMixed jm{};
+    JRecPair32 jp{};
     JRecF64 jd{};
     // [nc + 1] device copies of the cluster offsets, host copy too
     int64_t *d_off = nullptr;

@@ -7,8 +7,10 @@ workspace) and the stream.  The library must have been built
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
+import sys
 
 import torch
 
@@ -52,7 +54,7 @@ class ProfileTimes(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("lanes_per_i", C.c_int32), ("waves", C.c_int32), ("split", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("i_per_lane", C.c_int32)]
 
 
 EXPORTS = [
@@ -62,6 +64,7 @@ EXPORTS = [
     "nbody_set_launch", "nbody_get_launch", "nbody_set_step_loop", "nbody_strerror",
     "nbody_last_error",
     "nbody_profile", "nbody_profile_force_log",
+    "nbody_get_tuning", "nbody_set_tuning",
 ]
 
 
@@ -96,6 +99,8 @@ def load():
         "nbody_energy": (C.c_int, [vp, P(d), P(d), P(d)]),
         "nbody_autotune": (C.c_int, [vp, d]),
         "nbody_set_launch": (C.c_int, [vp, P(Launch)]),
+        "nbody_get_tuning": (C.c_int, [vp, P(Launch), i32]),
+        "nbody_set_tuning": (C.c_int, [vp, P(Launch), i32]),
         "nbody_get_launch": (C.c_int, [vp, i64, P(Launch)]),
         "nbody_set_step_loop": (C.c_int, [vp, i64]),
         "nbody_profile": (C.c_int, [vp, C.c_int, P(ProfileTimes)]),
@@ -174,6 +179,20 @@ class System:
         self.ctx = ctx
 
     # ------------------------------------------------------------ helpers
+    @contextlib.contextmanager
+    def _on_ctx_stream(self):
+        """Run a call on the context's stream: it first waits for the work
+        the caller queued on the current stream (inputs), temporaries are
+        allocated on it, and the current stream then waits for it (outputs)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur == self.stream:
+            yield
+            return
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            yield
+        cur.wait_stream(self.stream)
+
     def _check(self, rc):
         if rc != OK:
             msg = load().nbody_last_error(self.ctx).decode()
@@ -185,6 +204,10 @@ class System:
             self.ctx = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down (the runtime's own
+        # teardown may already be under way): close() systems explicitly
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -194,33 +217,39 @@ class System:
     def force(self, idx, out=None, pot=True):
         """a, da, d2a, potential of particles ``idx`` (ascending) from the
         stored state of all sources of their cluster."""
-        idx = _dev_i32(idx, self.device)
-        na = idx.shape[0]
-        if out is None:
-            out = [torch.empty((na, 3), dtype=torch.float64, device=self.device) for _ in range(3)]
-            out.append(torch.empty(na, dtype=torch.float64, device=self.device) if pot else None)
-        rc = load().nbody_force(self.ctx, na, _ptr(idx), *[_ptr(o) for o in out])
-        self._check(rc)
+        with self._on_ctx_stream():
+            idx = _dev_i32(idx, self.device)
+            na = idx.shape[0]
+            if out is None:
+                out = [torch.empty((na, 3), dtype=torch.float64, device=self.device)
+                       for _ in range(3)]
+                out.append(torch.empty(na, dtype=torch.float64, device=self.device) if pot else None)
+            rc = load().nbody_force(self.ctx, na, _ptr(idx), *[_ptr(o) for o in out])
+            self._check(rc)
         return tuple(out)
 
     def predict(self, t):
-        outs = [torch.empty((self.n, 3), dtype=torch.float64, device=self.device) for _ in range(3)]
-        self._check(load().nbody_predict(self.ctx, float(t), *[_ptr(o) for o in outs]))
+        with self._on_ctx_stream():
+            outs = [torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+                    for _ in range(3)]
+            self._check(load().nbody_predict(self.ctx, float(t), *[_ptr(o) for o in outs]))
         return tuple(outs)
 
     def schedule(self, t_target):
-        idx = torch.empty(self.n, dtype=torch.int32, device=self.device)
-        na, tn = C.c_int64(0), C.c_double(0.0)
-        self._check(load().nbody_schedule(self.ctx, float(t_target), _ptr(idx), C.byref(na),
-                                          C.byref(tn)))
+        with self._on_ctx_stream():
+            idx = torch.empty(self.n, dtype=torch.int32, device=self.device)
+            na, tn = C.c_int64(0), C.c_double(0.0)
+            self._check(load().nbody_schedule(self.ctx, float(t_target), _ptr(idx), C.byref(na),
+                                              C.byref(tn)))
         return idx[: na.value], tn.value
 
     def correct(self, idx, t_target, acc, jrk, snp):
-        idx = _dev_i32(idx, self.device)
-        na = idx.shape[0]
-        ins = [_dev_f64(q, (na, 3), self.device) for q in (acc, jrk, snp)]
-        self._check(load().nbody_correct(self.ctx, na, _ptr(idx), float(t_target),
-                                         *[_ptr(q) for q in ins]))
+        with self._on_ctx_stream():
+            idx = _dev_i32(idx, self.device)
+            na = idx.shape[0]
+            ins = [_dev_f64(q, (na, 3), self.device) for q in (acc, jrk, snp)]
+            self._check(load().nbody_correct(self.ctx, na, _ptr(idx), float(t_target),
+                                             *[_ptr(q) for q in ins]))
 
     def block_step(self, t_target):
         na, tb = C.c_int64(0), C.c_double(0.0)
@@ -235,32 +264,69 @@ class System:
 
     def get_state(self):
         n = self.n
-        vec = [torch.empty((n, 3), dtype=torch.float64, device=self.device) for _ in range(6)]
-        sc = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
-        self._check(load().nbody_get_state(self.ctx, *[_ptr(q) for q in vec + sc]))
+        with self._on_ctx_stream():
+            vec = [torch.empty((n, 3), dtype=torch.float64, device=self.device) for _ in range(6)]
+            sc = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
+            self._check(load().nbody_get_state(self.ctx, *[_ptr(q) for q in vec + sc]))
         keys = ("x", "v", "a", "jk", "sn", "cr", "t", "dt")
         return dict(zip(keys, vec + sc))
 
     def set_state(self, x=None, v=None, a=None, jk=None, sn=None, cr=None, t=None, dt=None):
         n = self.n
-        vec = [None if q is None else _dev_f64(q, (n, 3), self.device) for q in (x, v, a, jk, sn, cr)]
-        sc = [None if q is None else _dev_f64(q, (n,), self.device) for q in (t, dt)]
-        self._check(load().nbody_set_state(self.ctx, *[_ptr(q) for q in vec + sc]))
-        # the copies are queued on the context's stream; keep any temporaries
-        # alive until the next call (later work on that stream is ordered
-        # after the copies, so the caching allocator may reuse them safely)
-        self._keep = vec + sc
+        with self._on_ctx_stream():
+            vec = [None if q is None else _dev_f64(q, (n, 3), self.device)
+                   for q in (x, v, a, jk, sn, cr)]
+            sc = [None if q is None else _dev_f64(q, (n,), self.device) for q in (t, dt)]
+            self._check(load().nbody_set_state(self.ctx, *[_ptr(q) for q in vec + sc]))
+            # the copies are queued on the context's stream; temporaries made
+            # here belong to that stream, so the caching allocator reuses them
+            # only after the copies
+            for q in vec + sc:
+                if q is not None:
+                    q.record_stream(self.stream)
 
     def energy(self):
         ek, ep, L = C.c_double(0), C.c_double(0), (C.c_double * 3)()
         self._check(load().nbody_energy(self.ctx, C.byref(ek), C.byref(ep), L))
         return ek.value, ep.value, [L[0], L[1], L[2]]
 
-    def autotune(self, max_ms=200.0):
+    def autotune(self, max_ms=200.0, cache=None):
+        """Measure launch shapes (nbody_autotune).  With ``cache`` (a JSON
+        file path) a table stored there for the same system shape,
+        precision and device is loaded instead of measuring, and a new
+        measurement is stored."""
+        import json
+        key = {"n": self.n, "clusters": None if self._offsets is None else list(self._offsets),
+               "precision": int(self.cfg.precision),
+               "device": torch.cuda.get_device_name(self.device)}
+        if cache is not None and os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+            if data.get("key") == key:
+                self.set_tuning(data["table"])
+                return
         self._check(load().nbody_autotune(self.ctx, float(max_ms)))
+        if cache is not None:
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump({"key": key, "table": self.get_tuning()}, f)
+            os.replace(tmp, cache)
 
-    def set_launch(self, lanes_per_i=0, waves=0, split=0):
-        sh = Launch(int(lanes_per_i), int(waves), int(split), 0)
+    def get_tuning(self):
+        """The autotuner's table: [(lanes_per_i, waves, split, i_per_lane)]
+        per power of two of N_act (zeros: no tuned shape)."""
+        tab = (Launch * 40)()
+        cnt = load().nbody_get_tuning(self.ctx, tab, 40)
+        if cnt < 0:
+            self._check(int(cnt))
+        return [(e.lanes_per_i, e.waves, e.split, e.i_per_lane) for e in tab[:cnt]]
+
+    def set_tuning(self, table):
+        tab = (Launch * max(1, len(table)))(*[Launch(*map(int, e)) for e in table])
+        self._check(load().nbody_set_tuning(self.ctx, tab, len(table)))
+
+    def set_launch(self, lanes_per_i=0, waves=0, split=0, i_per_lane=0):
+        sh = Launch(int(lanes_per_i), int(waves), int(split), int(i_per_lane))
         self._check(load().nbody_set_launch(self.ctx, C.byref(sh)))
 
     def set_step_loop(self, max_active=-1):
@@ -294,4 +360,4 @@ class System:
     def get_launch(self, n_act):
         sh = Launch()
         self._check(load().nbody_get_launch(self.ctx, int(n_act), C.byref(sh)))
-        return sh.lanes_per_i, sh.waves, sh.split
+        return sh.lanes_per_i, sh.waves, sh.split, sh.i_per_lane

@@ -76,7 +76,7 @@ def term_sums(m, x, v, a, eps, idx, j_range=None):
 # where plain is set, also |got - ref| <= plain |ref| on rows whose reference
 # is not zero.  The reasoning is in the docstring of test_gpu_force.py.
 FORCE_TOL = {
-    0: ((1e-11, 1e-6), (1e-6, None), (2e-6, None), (1e-11, 1e-6)),      # mixed
+    0: ((1e-11, 1e-6), (1e-11, 1e-6), (2e-6, None), (1e-11, 1e-6)),     # mixed
     1: ((1e-12, 1e-11), (1e-12, 1e-11), (1e-11, 1e-10), (1e-12, 1e-11)),  # FP64
     2: ((1e-6, None), (1e-6, None), (2e-6, None), (1e-6, None)),        # FP32 pairs
 }

@@ -516,10 +516,24 @@ def _default(o):
     return str(o)
 
 
+def _close_systems():
+    """Release every GPU system the run left alive (so that no library call
+    runs from a destructor while the interpreter shuts down)."""
+    import gc
+
+    from paper_1207_2367_amd import System
+    gc.collect()
+    for o in gc.get_objects():
+        if isinstance(o, System):
+            o.close()
+    torch.cuda.synchronize()
+
+
 if __name__ == "__main__":
     # each argument: NAME or NAME:ARG[:ARG...] (positional arguments of the run)
     for spec in sys.argv[1:]:
         name, *args = spec.split(":")
         _log(f"scenario {spec}")
         out = RUNS[name](*args)
+        _close_systems()
         print(json.dumps(out, default=_default), flush=True)

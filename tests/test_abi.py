@@ -95,3 +95,6 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.nbody_set_launch(None, None) == nbody.EINVAL
     assert lib.nbody_step(None, 1.0, None) == nbody.EINVAL
     assert lib.nbody_autotune(None, 10.0) == nbody.EINVAL
+    assert lib.nbody_get_tuning(None, None, 0) == nbody.EINVAL
+    assert lib.nbody_set_tuning(None, None, 0) == nbody.EINVAL
+

@@ -15,11 +15,12 @@ roundings (difference, r^2, rsqrt, r^-3, alpha, beta, products), i.e. at
 most ~16 u = 1e-6 relative; a sum of such terms is off by at most that
 times S_i.  The snap pair term has one more cancelling level
 (-6 alpha J - 3 beta A): 2e-6.  Terms computed in FP64 (the mixed mode's
-acceleration and potential: 1/r from an FP32 seed and one Newton step,
-~1e-14) get 1e-11; the FP64 mode 1e-12 (1e-11 snap).  Where a plain
-per-particle bound is stated (FORCE_TOL's second entry) it is asserted as
-well on every row with a non-zero reference.  The tests print the plain
-max / p99 errors and the fraction within 1e-6.
+acceleration, jerk and potential: 1/r from an FP32 seed and one Newton
+step, ~1e-14) get 1e-11; the FP64 mode 1e-12 (1e-11 snap).  Where a plain
+per-particle bound is stated (FORCE_TOL's second entry: 1e-6 for the mixed
+mode's a, da and potential) it is asserted as well on every row with a
+non-zero reference.  The tests print the plain max / p99 errors and the
+fraction within 1e-6.
 """
 import numpy as np
 import pytest
@@ -64,8 +65,9 @@ def test_force_parity(inputs, prec, n_act):
 
 @pytest.mark.parametrize("prec", PRECS, ids=IDS)
 def test_force_every_launch_shape(inputs, prec):
-    """Each lanes-per-particle / waves / split-source shape gives the same
-    result to the tolerance (fixed-order reductions)."""
+    """Each lanes-per-particle / waves / split-source / particles-per-lane
+    shape gives the same result to the tolerance (fixed-order reductions);
+    150 active particles leave the last i-block of every shape ragged."""
     m, x, v, a = inputs
     n = m.shape[0]
     idx = ics.active_subset(n, 150, 5)
@@ -75,11 +77,13 @@ def test_force_every_launch_shape(inputs, prec):
     for lpi in (1, 2, 4, 8, 16, 32, 64):
         for waves in (1, 2, 4):
             for split in (1, 3, 16):
-                log_case(test="launch_shape", prec=prec, lpi=lpi, waves=waves, split=split)
-                s.set_launch(lpi, waves, split)
-                got = force(s, idx)
-                torch.cuda.synchronize()
-                _check(prec, got, ref, S)
+                for ipt in ((1, 2) if lpi <= 4 else (1,)):
+                    log_case(test="launch_shape", prec=prec, lpi=lpi, waves=waves, split=split,
+                             ipt=ipt)
+                    s.set_launch(lpi, waves, split, ipt)
+                    got = force(s, idx)
+                    torch.cuda.synchronize()
+                    _check(prec, got, ref, S)
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=IDS)
@@ -203,5 +207,31 @@ def test_force_full_size_sampled(prec):
         log_case(test="full_size", prec=prec, n=n, launch=s.get_launch(n))
         got = [cpu(q) for q in force(s, idx)]
         _check(prec, [g[sample] for g in got], ref, S)
-        scale = np.abs(mm * got[0]).sum()
-        assert np.abs((mm * got[0]).sum(0)).max() < (1e-6 if prec == 2 else 1e-13) * scale
+        # third law: sum_i m_i a_i = sum_i m_i da_i = 0 (FP64 sums in the
+        # mixed and FP64 modes)
+        for q in (0, 1):
+            scale = np.abs(mm * got[q]).sum()
+            assert np.abs((mm * got[q]).sum(0)).max() < (1e-6 if prec == 2 else 1e-13) * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_force_active_sets_65536(prec):
+    """The force microbenchmark's system (Plummer N = 65,536, seed 2002)
+    with its active-set sizes N_act = 1, 64, 1024, 8192, 65,536 (seeded
+    random subsets, automatic launch shapes): up to 512 active particles
+    per set against the oracle one by one.  The mixed mode must meet the
+    plain per-particle bound 1e-6 on a, da and the potential (and its
+    snap the k S_i bound); the printed lines give the plain max / p99 of
+    every quantity."""
+    n = 65536
+    m, x, v, a = plummer_inputs(n, 2002)
+    s = gpu_system(m, x, v, a, EPS, prec)
+    for n_act in (1, 64, 1024, 8192, 65536):
+        idx = ics.active_subset(n, n_act, 2003)
+        pos = np.arange(n_act) if n_act <= 512 else np.sort(
+            np.random.default_rng(n_act).choice(n_act, 512, replace=False))
+        smp = idx[pos]
+        log_case(test="active_sets_65536", prec=prec, n_act=n_act, launch=s.get_launch(n_act))
+        ref = oracle.force(m, x, v, a, EPS, smp)
+        got = [cpu(q)[pos] for q in force(s, idx)]
+        _check(prec, got, ref, term_sums(m, x, v, a, EPS, smp))

@@ -313,3 +313,59 @@ def test_error_paths():
     with pytest.raises(NBodyError) as e:
         System(np.array([0.4, 0.4, 0.2]), xx, vv, 0.0, dt_min=2.0 ** -10)
     assert e.value.code == -4
+
+
+def test_energy_requires_common_time():
+    """The energy sums of Sect. 5.1 are defined at a common time: with the
+    particles of a cluster at different times nbody_energy returns ESTATE
+    (and computes nothing); clusters may each sit at their own time."""
+    from paper_1207_2367_amd import NBodyError
+    m, x, v = ics.plummer(512, 5)
+    s = _system(m, x, v, 1)
+    e0 = s.energy()
+    t = np.zeros(512)
+    t[100:] = 1.0 / 16
+    s.set_state(t=t)
+    with pytest.raises(NBodyError) as e:
+        s.energy()
+    assert e.value.code == -5
+    s.set_state(t=np.full(512, 1.0 / 16))
+    assert s.energy()[:2] == e0[:2]          # same positions and velocities
+    sizes = [200, 312]
+    mc, xc, vc, off = ics.king_ensemble(2, sizes=sizes)
+    sc = _system(mc, xc, vc, 1, offsets=off)
+    tc = np.zeros(512)
+    tc[off[1]:] = 1.0 / 16                   # each cluster at one time
+    sc.set_state(t=tc)
+    sc.energy()
+    tc[off[1] + 5] = 0.0
+    sc.set_state(t=tc)
+    with pytest.raises(NBodyError) as e:
+        sc.energy()
+    assert e.value.code == -5
+
+
+def test_correct_rejects_bad_index_lists():
+    """nbody_correct with a list index outside [0, n) skips it and returns
+    EINVAL (the other particles are corrected); with validate on, a list out
+    of range or not ascending is refused before any change."""
+    from paper_1207_2367_amd import NBodyError
+    n = 600
+    m, x, v, a, jk, sn, cr, t, dt = _random_state(n, 23)
+    t[:] = 0.0
+    dt[:] = 1.0 / 16
+    a1, j1, s1 = a[:2] + 1e-3, jk[:2], sn[:2]
+    s = _system(m, x, v, 1)
+    s.set_state(x=x, v=v, a=a, jk=jk, sn=sn, cr=cr, t=t, dt=dt)
+    with pytest.raises(NBodyError) as e:
+        s.correct([3, n + 7], 1.0 / 16, a1, j1, s1)
+    assert e.value.code == -1
+    g = s.get_state()
+    assert cpu(g["t"])[3] == 1.0 / 16 and (cpu(g["t"])[4:] == 0).all()
+    sv = _system(m, x, v, 1, validate=True)
+    sv.set_state(x=x, v=v, a=a, jk=jk, sn=sn, cr=cr, t=t, dt=dt)
+    for bad in ([5, 3], [3, n], [-1, 3], [4, 4]):
+        with pytest.raises(NBodyError) as e:
+            sv.correct(bad, 1.0 / 16, a1, j1, s1)
+        assert e.value.code == -1
+    assert (cpu(sv.get_state()["t"]) == 0).all()
