@@ -142,6 +142,28 @@ void nbody_free(nbody_ctx *ctx);
 int nbody_force(nbody_ctx *ctx, int64_t n_act, const int32_t *d_idx,
                 double *d_acc, double *d_jrk, double *d_snp, double *d_pot);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   evaluation of nbody_force without a context or workspace.  Sources are
+   the caller's arrays d_mass[n], d_pos/d_vel/d_acc[n][3] (row-major FP64,
+   one system, softening eps >= 0, evaluation precision as in
+   nbody_config); outputs, index list and NULL rules as for nbody_force
+   (d_idx strictly ascending in [0, n), not checked).  The source records
+   and split-source partials live in a fixed 64 MiB device array inside the
+   library, one per GPU, kept until the process ends; the call allocates
+   nothing.  Limit: n * R + 80 * n_act plus about 1 KiB within 64 MiB,
+   R = 68 (mixed), 56 (FP32 pair), 80 (FP64) bytes -- e.g. up to
+   n = n_act = 2^18 in every precision.  Asynchronous on the stream
+   (a hipStream_t, NULL = default).  Calls that overlap on one GPU share
+   that array and race: order them on one stream.
+   Errors: EINVAL (sizes beyond the limit, n_act > n, NULL pointer, bad
+   eps or precision), EDEVICE.                                            */
+int nbody_force_noalloc(int64_t n, const double *d_mass, const double *d_pos,
+                        const double *d_vel, const double *d_acc, double eps,
+                        int32_t precision, int64_t n_act, const int32_t *d_idx,
+                        double *d_acc_out, double *d_jrk_out, double *d_snp_out,
+                        double *d_pot_out, void *stream);
+
 /* Prediction step alone (paper Sect. 3, item 1): Taylor series of every
    particle's position, velocity and acceleration from its own time t_i
    to time t (h = t - t_i), written to d_pos/d_vel/d_acc[n][3] in FP64.

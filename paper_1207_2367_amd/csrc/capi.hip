@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 
@@ -18,6 +19,15 @@ using namespace nb;
 struct nbody_ctx {
     Ctx c;
 };
+
+// Scratch of nbody_force_noalloc: the source records, the one-cluster work
+// tables and the split-source partials of one evaluation, in a fixed device
+// array instead of a caller workspace.  Each device the library runs on
+// holds its own copy until the process ends.  Host code never uses the
+// array's name as an address: the device address is looked up once per
+// device (scratch_address below) and only that address is passed on.
+constexpr int64_t NOALLOC_SCRATCH_BYTES = int64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -107,6 +117,66 @@ int take_err(Ctx &c)
     if (e & ERR_STATE)
         return fail(c, NBODY_ESTATE, "the particles of a cluster are not at one time");
     return fail(c, NBODY_EINVAL, "index list out of range / not ascending, or a particle is past the target time");
+}
+
+// device address of the current device's copy of the scratch array (looked
+// up with hipGetSymbolAddress on the first call on each device)
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_addr[NOALLOC_MAX_DEVICES] = {};
+
+hipError_t scratch_address(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_addr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+// Scratch layout of nbody_force_noalloc for n sources: the records of the
+// context's precision, seg[2] and off[2]; the split partials follow at the
+// returned offset.  With base == nullptr only the size is computed.
+int64_t noalloc_layout(int64_t n, int32_t prec, Ctx *c, unsigned char *base, int64_t **seg,
+                       int64_t **off)
+{
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) -> unsigned char * {
+        unsigned char *p = base ? base + o : nullptr;
+        o += align_up(bytes);
+        return p;
+    };
+    const int64_t d = sizeof(double), f = sizeof(float);
+    if (prec == NBODY_PREC_MIXED) {
+        double **dl[7] = {&c->jm.x, &c->jm.y, &c->jm.z, &c->jm.m, &c->jm.vx, &c->jm.vy, &c->jm.vz};
+        for (auto p : dl)
+            *p = (double *)take(n * d);
+        float **fl[3] = {&c->jm.ax, &c->jm.ay, &c->jm.az};
+        for (auto p : fl)
+            *p = (float *)take(n * f);
+    } else if (prec == NBODY_PREC_FP32PAIR) {
+        double **dl[4] = {&c->jp.x, &c->jp.y, &c->jp.z, &c->jp.m};
+        for (auto p : dl)
+            *p = (double *)take(n * d);
+        float **fl[6] = {&c->jp.vx, &c->jp.vy, &c->jp.vz, &c->jp.ax, &c->jp.ay, &c->jp.az};
+        for (auto p : fl)
+            *p = (float *)take(n * f);
+    } else {
+        double **dl[10] = {&c->jd.x, &c->jd.y, &c->jd.z, &c->jd.vx, &c->jd.vy,
+                           &c->jd.vz, &c->jd.ax, &c->jd.ay, &c->jd.az, &c->jd.m};
+        for (auto p : dl)
+            *p = (double *)take(n * d);
+    }
+    *seg = (int64_t *)take(2 * 8);
+    *off = (int64_t *)take(2 * 8);
+    return o;
 }
 
 }  // namespace
@@ -1153,6 +1223,66 @@ int nbody_profile(nbody_ctx *ctx, int enable, nbody_profile_times *out)
         c.flog_ms.clear();
     }
     c.prof = enable != 0;
+    return NBODY_OK;
+}
+
+int nbody_force_noalloc(int64_t n, const double *d_mass, const double *d_pos,
+                        const double *d_vel, const double *d_acc, double eps, int32_t precision,
+                        int64_t n_act, const int32_t *d_idx, double *d_acc_out,
+                        double *d_jrk_out, double *d_snp_out, double *d_pot_out, void *stream)
+{
+    if (n <= 0 || n > (int64_t(1) << 31) - 1 || n_act < 0 || n_act > n || !(eps >= 0.0) ||
+        !std::isfinite(eps) ||
+        (precision != NBODY_PREC_MIXED && precision != NBODY_PREC_FP64 &&
+         precision != NBODY_PREC_FP32PAIR))
+        return NBODY_EINVAL;
+    if (n_act == 0)
+        return NBODY_OK;
+    if (!d_mass || !d_pos || !d_vel || !d_acc || !d_idx || !d_acc_out || !d_jrk_out ||
+        !d_snp_out)
+        return NBODY_EINVAL;
+    // host-side description of the evaluation: no workspace, no state
+    Ctx c;
+    c.n = n;
+    c.nc = 1;
+    c.eps = eps;
+    nbody_default_config(&c.cfg);
+    c.cfg.precision = precision;
+    c.cfg.stream = stream;
+    c.stream = (hipStream_t)stream;
+    int64_t *seg = nullptr, *off = nullptr;
+    const int64_t head = noalloc_layout(n, precision, &c, nullptr, &seg, &off);
+    const int64_t cap = (NOALLOC_SCRATCH_BYTES - head) / (10 * (int64_t)sizeof(double));
+    if (cap < n_act)
+        return NBODY_EINVAL;   // records plus one split of partials exceed the scratch
+    if (hipGetDevice(&c.device) != hipSuccess)
+        return NBODY_EDEVICE;
+    unsigned char *base = nullptr;
+    if (scratch_address(c.device, &base) != hipSuccess)
+        return NBODY_EDEVICE;
+    noalloc_layout(n, precision, &c, base, &seg, &off);
+    c.part = reinterpret_cast<double *>(base + head);
+    c.part_cap = cap;
+    const Launch L = rule_launch(n_act, n, cap, precision);
+    const int64_t ib = iblock_size(L);
+    ForceWork w{};
+    w.idx = d_idx;
+    w.seg = seg;
+    w.off = off;
+    w.split = L.split;
+    w.nc = 1;
+    w.n_blocks = (n_act + ib - 1) / ib;
+    ForceOut out{};
+    out.vec[0] = d_acc_out;
+    out.vec[1] = d_jrk_out;
+    out.vec[2] = d_snp_out;
+    out.pot = d_pot_out;
+    out.sk = 3;
+    out.sd = 1;
+    if (launch_pack_arrays(c, d_mass, d_pos, d_vel, d_acc, n_act, seg, off, c.stream) !=
+            hipSuccess ||
+        launch_force(c, w, L, out, n_act, c.stream) != hipSuccess)
+        return NBODY_EDEVICE;
     return NBODY_OK;
 }
 

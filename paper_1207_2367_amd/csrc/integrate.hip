@@ -1151,7 +1151,53 @@ __global__ void check_finite_kernel(State st, int64_t n, uint32_t *err)
 
 unsigned nblk(int64_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
 
+// Source records straight from caller arrays (mass[n], pos/vel/acc [n][3]
+// row-major), at their own time: the records nbody_force builds from a
+// context's stored state, for the evaluation that keeps no context.  Also
+// writes the one-cluster work tables seg = {0, n_act}, off = {0, n}.
+__global__ __launch_bounds__(TPB) void pack_arrays_kernel(const double *mass, const double *pos,
+                                                          const double *vel, const double *acc,
+                                                          JRecMixed jm, JRecPair32 jp, JRecF64 jd,
+                                                          int prec, int64_t n, int64_t n_act,
+                                                          int64_t *seg, int64_t *off)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i == 0) {
+        seg[0] = 0;
+        seg[1] = n_act;
+        off[0] = 0;
+        off[1] = n;
+    }
+    if (i >= n)
+        return;
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
+    const double ax = acc[3 * i], ay = acc[3 * i + 1], az = acc[3 * i + 2];
+    if (prec == NBODY_PREC_MIXED) {
+        jm.x[i] = x; jm.y[i] = y; jm.z[i] = z; jm.m[i] = mass[i];
+        jm.vx[i] = vx; jm.vy[i] = vy; jm.vz[i] = vz;
+        jm.ax[i] = (float)ax; jm.ay[i] = (float)ay; jm.az[i] = (float)az;
+    } else if (prec == NBODY_PREC_FP32PAIR) {
+        jp.x[i] = x; jp.y[i] = y; jp.z[i] = z; jp.m[i] = mass[i];
+        jp.vx[i] = (float)vx; jp.vy[i] = (float)vy; jp.vz[i] = (float)vz;
+        jp.ax[i] = (float)ax; jp.ay[i] = (float)ay; jp.az[i] = (float)az;
+    } else {
+        jd.x[i] = x; jd.y[i] = y; jd.z[i] = z; jd.m[i] = mass[i];
+        jd.vx[i] = vx; jd.vy[i] = vy; jd.vz[i] = vz;
+        jd.ax[i] = ax; jd.ay[i] = ay; jd.az[i] = az;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pack_arrays(const Ctx &c, const double *mass, const double *pos,
+                              const double *vel, const double *acc, int64_t n_act,
+                              int64_t *seg, int64_t *off, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_arrays_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s, mass, pos, vel, acc,
+                       c.jm, c.jp, c.jd, (int)c.cfg.precision, c.n, n_act, seg, off);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
                        const int32_t *cluster_of, hipStream_t s)

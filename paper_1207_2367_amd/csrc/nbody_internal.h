@@ -112,6 +112,11 @@ int64_t iblock_size(const Launch &L);
 // integrate.hip
 hipError_t launch_pack(const Ctx &c, const double *T_cluster, int own_time,
                        const int32_t *cluster_of, hipStream_t s);
+// records of c.n particles from caller arrays (c.jm / c.jp / c.jd per the
+// precision), plus seg = {0, n_act} and off = {0, c.n}
+hipError_t launch_pack_arrays(const Ctx &c, const double *mass, const double *pos,
+                              const double *vel, const double *acc, int64_t n_act,
+                              int64_t *seg, int64_t *off, hipStream_t s);
 hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel,
                               double *acc, hipStream_t s);
 hipError_t launch_schedule(const Ctx &c, double t_target, int64_t seq, hipStream_t s);

@@ -63,7 +63,7 @@ EXPORTS = [
     "nbody_step", "nbody_get_state", "nbody_set_state", "nbody_energy", "nbody_autotune",
     "nbody_set_launch", "nbody_get_launch", "nbody_set_step_loop", "nbody_strerror",
     "nbody_last_error",
-    "nbody_profile", "nbody_profile_force_log",
+    "nbody_profile", "nbody_profile_force_log", "nbody_force_noalloc",
     "nbody_get_tuning", "nbody_set_tuning",
 ]
 
@@ -107,6 +107,8 @@ def load():
         "nbody_profile_force_log": (i64, [vp, i64, vp, vp, vp]),
         "nbody_strerror": (C.c_char_p, [C.c_int]),
         "nbody_last_error": (C.c_char_p, [vp]),
+        "nbody_force_noalloc": (C.c_int, [i64, vp, vp, vp, vp, d, i32, i64, vp, vp, vp, vp, vp,
+                                          vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,6 +143,34 @@ def _dev_f64(t, shape, device):
 
 def _dev_i32(t, device):
     return torch.as_tensor(t, device=device).to(torch.int32).contiguous()
+
+
+def force_noalloc(mass, pos, vel, acc, eps, idx, precision=PREC_MIXED, out=None, pot=True,
+                  device="cuda"):
+    """nbody_force_noalloc: a, da, d2a (and the potential) of particles
+    ``idx`` against the given arrays, with no context or workspace.  Inputs
+    are taken as device FP64 tensors (copied there if they are not); the
+    call is queued on the current stream."""
+    dev = torch.device(device)
+    m = _dev_f64(mass, (-1,), dev)
+    n = m.shape[0]
+    x, v, a = (_dev_f64(q, (n, 3), dev) for q in (pos, vel, acc))
+    idx = _dev_i32(idx, dev)
+    na = idx.shape[0]
+    if out is None:
+        out = [torch.empty((na, 3), dtype=torch.float64, device=dev) for _ in range(3)]
+        out.append(torch.empty(na, dtype=torch.float64, device=dev) if pot else None)
+    stream = torch.cuda.current_stream(dev)
+    rc = load().nbody_force_noalloc(n, _ptr(m), _ptr(x), _ptr(v), _ptr(a), float(eps),
+                                    int(precision), na, _ptr(idx), *[_ptr(o) for o in out],
+                                    C.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise NBodyError(rc, load().nbody_strerror(rc).decode())
+    # the inputs may be temporaries of this call: keep them until the
+    # queued work is done
+    for t in (m, x, v, a, idx):
+        t.record_stream(stream)
+    return tuple(out)
 
 
 class System:

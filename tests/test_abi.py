@@ -98,3 +98,25 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.nbody_get_tuning(None, None, 0) == nbody.EINVAL
     assert lib.nbody_set_tuning(None, None, 0) == nbody.EINVAL
 
+
+def test_noalloc_arguments_rejected_before_device_work(lib):
+    """nbody_force_noalloc checks sizes against its fixed scratch (and its
+    other arguments) on the host, before any device call."""
+    from paper_1207_2367_amd import nbody
+    d = C.c_void_p(256)
+    args = (d, d, d, d)
+    outs = (d, d, d, None, None)
+    # 1,310,720 sources do not fit the 64 MiB scratch in any precision (56 B
+    # per source at the least)
+    for prec in (0, 1, 2):
+        assert lib.nbody_force_noalloc(5 << 18, *args, 1e-4, prec, 1, d, *outs) == nbody.EINVAL
+    # FP64 records (80 B) plus one split of partials (80 B per active
+    # particle): 450,000 sources all active exceed 64 MiB
+    assert lib.nbody_force_noalloc(450000, *args, 1e-4, 1, 450000, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, *args, -1.0, 0, 1, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, *args, float("inf"), 0, 1, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, *args, 1e-4, 7, 1, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, *args, 1e-4, 0, 5, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(0, *args, 1e-4, 0, 0, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, None, d, d, d, 1e-4, 0, 1, d, *outs) == nbody.EINVAL
+    assert lib.nbody_force_noalloc(4, *args, 1e-4, 0, 0, d, *outs) == nbody.OK
