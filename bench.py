@@ -241,7 +241,7 @@ def read_traffic():
         return None
     tot, kern = 0.0, None
     for name in ("FETCH_SIZE", "WRITE_SIZE"):
-        mm = re.search(r"# %s: .*dominant kernel dispatch \d+ \(([^,]+), grid (\d+), "
+        mm = re.search(r"# %s: .*dominant kernel dispatch \d+ \((.+?), grid (\d+), "
                        r"[\d.]+ ms\) [\d.e+]+ KiB -> ([\d.]+) MB per launch" % name, text)
         if not mm:
             return None
@@ -516,12 +516,15 @@ def main():
 
     achieved = FLOPS_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
     tr = read_traffic()
-    kname = (f"force_kernel<0, {launch[0]}, {launch[1]}, false, false>")
+    # the kernel as rocprofv3 names it: force_kernel<precision, lanes per
+    # particle, waves, eps == 0, potential, particles per lane group>, and
+    # its grid in work-items (x: N_act * lanes / particles per group; y: split)
+    kname = f"force_kernel<0, {launch[0]}, {launch[1]}, false, false, {max(1, launch[3])}>"
+    grid_x = args.n_act * launch[0] // max(1, launch[3])
     traffic = None
     traffic_note = "no counter summary of this kernel"
     if tr is not None:
-        if tr[1][0].startswith("void nb::force_kernel<0, %d, %d, false, false>" % launch[:2]) and \
-                tr[1][1] == args.n_act * launch[0]:
+        if tr[1][0] == "void nb::" + kname and tr[1][1] == grid_x * launch[2]:
             traffic = round(tr[0])
             traffic_note = ("FETCH_SIZE + WRITE_SIZE per launch of this kernel, each scaled by "
                             "what the counter reads for a 1 GiB copy; "
@@ -556,7 +559,7 @@ def main():
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),
             "traffic": traffic, "traffic_note": traffic_note,
             "algorithmic_bytes": args.n * 68 + args.n_act * (4 + 68 + 80),
-            "kernel": kname + f" grid {args.n_act * launch[0]} x {launch[2]}",
+            "kernel": kname + f" grid {grid_x} x {launch[2]}",
             "kernel_avg_ms": round(avg_ms, 4), "flops_per_pair": FLOPS_PER_PAIR,
             "peak_basis": "MI355X FP32 vector 157.3 TFLOP/s (counts packed FP32)",
             "nonpacked_ceiling": {"peak": round(PEAK_FP32_NONPACKED, 2),

@@ -50,3 +50,20 @@ def test_counter_calibration(tmp_path, capsys):
     out = capsys.readouterr().out
     # 1 GiB copy counts 524288 KiB -> factor 2; 1000 KiB -> 2.048 MB
     assert "factor 2.0000" in out and "-> 2.05 MB per launch" in out
+
+
+def test_read_traffic(tmp_path, monkeypatch):
+    """roofline.traffic comes from the two copy-calibrated counter lines of
+    the committed summary; the kernel's name and grid come with it."""
+    f = tmp_path / "c.txt"
+    name = "void nb::force_kernel<0, 1, 4, false, false, 2>"
+    f.write_text(
+        f"# FETCH_SIZE: 1 GiB copy (dispatch 4) counts 524300 KiB -> factor 2.0000; dominant kernel "
+        f"dispatch 52 ({name}, grid 524288, 923.932 ms) 2.59993e+06 KiB -> 5324.53 MB per launch\n"
+        f"# WRITE_SIZE: 1 GiB copy (dispatch 4) counts 1.04858e+06 KiB -> factor 1.0000; dominant "
+        f"kernel dispatch 52 ({name}, grid 524288, 922.122 ms) 81920 KiB -> 83.89 MB per launch\n")
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
+    tot, kern = bench.read_traffic()
+    assert abs(tot - 5408.42e6) < 1.0 and kern == (name, 524288)
+    f.write_text("nothing here\n")
+    assert bench.read_traffic() is None
