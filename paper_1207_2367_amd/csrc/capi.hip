@@ -243,8 +243,13 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     int32_t *blk_cl = (int32_t *)take((n + nc + 1) * 4);
     int64_t *blk_first = (int64_t *)take((nc + 1) * 8);
     int64_t *info = (int64_t *)take(64 * 8);
-    uint64_t *loop_min = (uint64_t *)take(LOOP_GMAX * 8);
-    int32_t *loop_cnt = (int32_t *)take(LOOP_GMAX * 4);
+    uint64_t *loop_min = (uint64_t *)take(2 * LOOP_GMAX * 8);
+    int32_t *loop_cnt = (int32_t *)take(2 * LOOP_GMAX * 4);
+    // ensemble plan: grp_of, first, size [LOOP_GMAX each], cl_off [LOOP_GMAX + 1],
+    // cl [nc]; part_off, part_cap [LOOP_GMAX each], seg [2 LOOP_GMAX]; results
+    int32_t *ens_i32 = nc > 1 ? (int32_t *)take((4 * LOOP_GMAX + 1 + nc) * 4) : nullptr;
+    int64_t *ens_i64 = nc > 1 ? (int64_t *)take(4 * LOOP_GMAX * 8) : nullptr;
+    unsigned long long *ens_res = nc > 1 ? (unsigned long long *)take(4 * 8) : nullptr;
     uint32_t *loop_bar = (uint32_t *)take(LOOP_BAR_WORDS * 4);
     uint32_t *err = (uint32_t *)take(4);
     const int64_t red_cap = 5 * (n / 256 + 2) + 16;
@@ -274,6 +279,9 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
         c->d_info = info;
         c->d_loop_min = loop_min;
         c->d_loop_cnt = loop_cnt;
+        c->d_ens_i32 = ens_i32;
+        c->d_ens_i64 = ens_i64;
+        c->d_ens_res = ens_res;
         c->d_loop_bar = loop_bar;
         c->d_err = err;
         c->d_red = red;
@@ -493,6 +501,140 @@ int wait_words(Ctx &c, int first, int count, int seq_word, int64_t seq, int64_t 
 }
 
 int wait_totals(Ctx &c, int64_t seq, int64_t tot[6]) { return wait_words(c, 0, 6, 6, seq, tot); }
+
+// Work split of the ensemble loop over G workgroups: a cluster whose share
+// of the estimated work (N_c^2) is at least two workgroups' worth gets a
+// group of its own, the largest power of two of workgroups within its
+// share (at most ENS_GROUP_MAX); the other clusters go to single-workgroup groups,
+// largest first onto the least loaded (longest-processing-time packing).
+// Each group's partial slots are twice its largest cluster, so the groups'
+// regions fit the split buffer (2 n slots).  Copies the tables to the
+// device and sets c.ens; returns the number of workgroups to launch.
+int plan_ensemble(Ctx &c, int G)
+{
+    const int nc = c.nc;
+    std::vector<int> order(nc);
+    for (int k = 0; k < nc; ++k)
+        order[k] = k;
+    auto work = [&](int k) {
+        const double s = (double)(c.off[k + 1] - c.off[k]);
+        return s * s;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    double total = 0.0;
+    for (int k = 0; k < nc; ++k)
+        total += work(k);
+    std::vector<std::vector<int>> groups;   // clusters of each group
+    std::vector<int> gsize;
+    int used = 0;
+    size_t nbig = 0;
+    for (; nbig < order.size(); ++nbig) {
+        const double share = total > 0.0 ? work(order[nbig]) / total * G : 0.0;
+        int W = 1;
+        while (W * 2 <= share && W * 2 <= ENS_GROUP_MAX)
+            W *= 2;
+        // keep at least one workgroup for every cluster not yet placed
+        const int rest = (int)std::min<size_t>(order.size() - nbig - 1, (size_t)G);
+        while (W > 1 && used + W + (rest > 0 ? 1 : 0) > G)
+            W /= 2;
+        if (W < 2)
+            break;
+        groups.push_back({order[nbig]});
+        gsize.push_back(W);
+        used += W;
+    }
+    const int nsingle = std::min<int>(G - used, (int)(order.size() - nbig));
+    std::vector<double> load(nsingle, 0.0);
+    const size_t g0 = groups.size();
+    for (int k = 0; k < nsingle; ++k) {
+        groups.push_back({});
+        gsize.push_back(1);
+    }
+    for (size_t q = nbig; q < order.size(); ++q) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        groups[g0 + b].push_back(order[q]);
+        load[b] += work(order[q]);
+    }
+    const int ng = (int)groups.size();
+    std::vector<int32_t> i32(4 * LOOP_GMAX + 1 + nc, 0);
+    std::vector<int64_t> i64(4 * LOOP_GMAX, 0);
+    int32_t *grp_of = i32.data(), *first = grp_of + LOOP_GMAX, *size = first + LOOP_GMAX;
+    int32_t *cl_off = size + LOOP_GMAX, *cl = cl_off + LOOP_GMAX + 1;
+    int64_t *part_off = i64.data(), *part_cap = part_off + LOOP_GMAX;
+    int wg = 0, ncl = 0;
+    int64_t slot = 0;
+    for (int g = 0; g < ng; ++g) {
+        first[g] = wg;
+        size[g] = gsize[g];
+        for (int k = 0; k < gsize[g]; ++k)
+            grp_of[wg++] = g;
+        cl_off[g] = ncl;
+        int64_t big = 1;
+        for (int k : groups[g]) {
+            cl[ncl++] = k;
+            big = std::max<int64_t>(big, c.off[k + 1] - c.off[k]);
+        }
+        part_off[g] = slot;
+        part_cap[g] = 2 * big;
+        slot += 2 * big;
+    }
+    cl_off[ng] = ncl;
+    if (slot > c.part_cap || ncl != nc)
+        return 0;
+    if (hipMemcpyAsync(c.d_ens_i32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice,
+                       c.stream) != hipSuccess ||
+        hipMemcpyAsync(c.d_ens_i64, i64.data(), i64.size() * 8, hipMemcpyHostToDevice,
+                       c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+        return 0;
+    c.ens.grp_of = c.d_ens_i32;
+    c.ens.first = c.d_ens_i32 + LOOP_GMAX;
+    c.ens.size = c.d_ens_i32 + 2 * LOOP_GMAX;
+    c.ens.cl_off = c.d_ens_i32 + 3 * LOOP_GMAX;
+    c.ens.cl = c.d_ens_i32 + 4 * LOOP_GMAX + 1;
+    c.ens.part_off = c.d_ens_i64;
+    c.ens.part_cap = c.d_ens_i64 + LOOP_GMAX;
+    c.ens.seg = c.d_ens_i64 + 2 * LOOP_GMAX;
+    return wg;
+}
+
+// A batched context's block steps to t_target in one launch (the ensemble
+// loop); *done = false when the loop is not used (then the host-sized path
+// runs the steps).
+int run_ensemble(Ctx &c, double t_target, nbody_step_stats *stats, bool *done)
+{
+    *done = false;
+    if (c.nc <= 1 || c.loop_amax == 0 || c.pinned.lpi != 0 || c.prof)
+        return NBODY_OK;
+    if (c.ens_grid < 0) {
+        const int G = ensemble_max_grid(c);
+        c.ens_grid = G >= 1 ? plan_ensemble(c, G) : 0;
+    }
+    if (c.ens_grid <= 0)
+        return NBODY_OK;
+    HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 32 * c.ens_grid * sizeof(uint32_t), c.stream));
+    HIPCHK(c, hipMemsetAsync(c.d_ens_res, 0, 4 * 8, c.stream));
+    if (launch_ensemble_loop(c, t_target, c.ens_grid, c.ens, c.d_ens_res, c.stream) !=
+        hipSuccess) {
+        // the runtime refused the cooperative launch (nothing was enqueued):
+        // clear that error and keep to the host-sized path from now on
+        (void)hipGetLastError();
+        c.ens_grid = 0;
+        return NBODY_OK;
+    }
+    unsigned long long r[4];
+    HIPCHK(c, hipMemcpyAsync(r, c.d_ens_res, 4 * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    if (stats) {
+        stats->block_steps += (int64_t)r[2];
+        stats->active_total += (int64_t)r[0];
+        stats->interactions += (double)r[1];
+    }
+    if (int rc = take_err(c))
+        return rc;
+    *done = true;
+    return NBODY_OK;
+}
 
 // Block steps inside one cooperative launch while the active sets stay at
 // or below the loop's limit (one system, no pinned shape, no profiling).
@@ -895,7 +1037,12 @@ int nbody_step(nbody_ctx *ctx, double t_target, nbody_step_stats *stats)
     int rc = take_err(c);
     if (rc)
         return rc;
-    for (;;) {
+    // independent clusters: every block step in one launch
+    bool done = false;
+    rc = run_ensemble(c, t_target, stats, &done);
+    if (rc)
+        return rc;
+    for (; !done;) {
         // small blocks inside one launch; a larger one on the host path
         int reason = 0;
         rc = run_loop(c, t_target, stats, &reason);

@@ -70,6 +70,28 @@ __device__ __forceinline__ double rinv_f64(double r2)
     return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
+// LDS tile of NT source records.  One per (precision, tile size): every
+// launch shape with that tile size uses the same LDS, so a kernel that runs
+// several shapes (the ensemble loop) holds one tile.
+template <int PREC, int NT>
+struct SrcTile {
+    static constexpr bool P32 = PREC == PREC_PAIR32, MIXED = PREC == PREC_MIXED;
+    static constexpr int NJ = PREC == PREC_INIT ? NT : 1;
+    using VV = typename std::conditional<P32, float, double>::type;
+    using VA = typename std::conditional<MIXED || P32, float, double>::type;
+    double x[NT], y[NT], z[NT], m[NT];
+    VV vx[NT], vy[NT], vz[NT];
+    VA ax[NT], ay[NT], az[NT];
+    double jx[NJ], jy[NJ], jz[NJ];   // sources' jerks: start-up evaluation only
+};
+
+template <int PREC, int NT>
+__device__ __forceinline__ SrcTile<PREC, NT> &src_tile()
+{
+    __shared__ SrcTile<PREC, NT> t;
+    return t;
+}
+
 // One workgroup's share of an evaluation: i-block g (IB active slots) against
 // source split b.  The launch kernel calls it with (blockIdx.x, blockIdx.y);
 // the device-resident block-step loop calls it for the units it takes.
@@ -100,10 +122,7 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
     using VV = typename std::conditional<P32, float, double>::type;
     using VA = typename std::conditional<MIXED || P32, float, double>::type;
 
-    __shared__ double s_x[NT], s_y[NT], s_z[NT], s_m[NT];
-    __shared__ VV s_vx[NT], s_vy[NT], s_vz[NT];
-    __shared__ VA s_ax[NT], s_ay[NT], s_az[NT];
-    __shared__ double s_jx[INIT ? NT : 1], s_jy[INIT ? NT : 1], s_jz[INIT ? NT : 1];
+    SrcTile<PREC, NT> &tl = src_tile<PREC, NT>();
 
     // ---- which active slots and which sources this workgroup takes
     int c = 0;
@@ -184,24 +203,24 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
         __syncthreads();
         const int64_t jj = t0 + tid;
         if (jj < j1) {
-            s_x[tid] = J.x[jj];
-            s_y[tid] = J.y[jj];
-            s_z[tid] = J.z[jj];
-            s_m[tid] = J.m[jj];
-            s_vx[tid] = J.vx[jj]; s_vy[tid] = J.vy[jj]; s_vz[tid] = J.vz[jj];
-            s_ax[tid] = J.ax[jj]; s_ay[tid] = J.ay[jj]; s_az[tid] = J.az[jj];
+            tl.x[tid] = J.x[jj];
+            tl.y[tid] = J.y[jj];
+            tl.z[tid] = J.z[jj];
+            tl.m[tid] = J.m[jj];
+            tl.vx[tid] = J.vx[jj]; tl.vy[tid] = J.vy[jj]; tl.vz[tid] = J.vz[jj];
+            tl.ax[tid] = J.ax[jj]; tl.ay[tid] = J.ay[jj]; tl.az[tid] = J.az[jj];
             if constexpr (INIT) {
-                s_jx[tid] = J.jx[jj]; s_jy[tid] = J.jy[jj]; s_jz[tid] = J.jz[jj];
+                tl.jx[tid] = J.jx[jj]; tl.jy[tid] = J.jy[jj]; tl.jz[tid] = J.jz[jj];
             }
         } else {
-            s_x[tid] = NULL_POS;
-            s_y[tid] = NULL_POS;
-            s_z[tid] = NULL_POS;
-            s_m[tid] = 0.0;
-            s_vx[tid] = 0; s_vy[tid] = 0; s_vz[tid] = 0;
-            s_ax[tid] = 0; s_ay[tid] = 0; s_az[tid] = 0;
+            tl.x[tid] = NULL_POS;
+            tl.y[tid] = NULL_POS;
+            tl.z[tid] = NULL_POS;
+            tl.m[tid] = 0.0;
+            tl.vx[tid] = 0; tl.vy[tid] = 0; tl.vz[tid] = 0;
+            tl.ax[tid] = 0; tl.ay[tid] = 0; tl.az[tid] = 0;
             if constexpr (INIT) {
-                s_jx[tid] = 0; s_jy[tid] = 0; s_jz[tid] = 0;
+                tl.jx[tid] = 0; tl.jy[tid] = 0; tl.jz[tid] = 0;
             }
         }
         __syncthreads();
@@ -221,9 +240,9 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
 #pragma unroll UNROLL
             for (int p = p0; p < p0 + FOLD; ++p) {
                 const int t = js + p * LPI;
-                const double sx = s_x[t], sy = s_y[t], sz = s_z[t], sm = s_m[t];
-                const VV svx = s_vx[t], svy = s_vy[t], svz = s_vz[t];
-                const VA sax = s_ax[t], say = s_ay[t], saz = s_az[t];
+                const double sx = tl.x[t], sy = tl.y[t], sz = tl.z[t], sm = tl.m[t];
+                const VV svx = tl.vx[t], svy = tl.vy[t], svz = tl.vz[t];
+                const VA sax = tl.ax[t], say = tl.ay[t], saz = tl.az[t];
 #pragma unroll
                 for (int u = 0; u < IPT; ++u) {
                     if constexpr (P32) {
@@ -315,8 +334,8 @@ __device__ __forceinline__ void force_block(const typename Smem<PREC>::R &J, con
                         const double beta = fma(alpha, alpha, qq * rinv2);
                         if constexpr (INIT) {
                             // start-up evaluation with the crackle, term by term
-                            const double djx = s_jx[t] - jxi[u], djy = s_jy[t] - jyi[u],
-                                         djz = s_jz[t] - jzi[u];
+                            const double djx = tl.jx[t] - jxi[u], djy = tl.jy[t] - jyi[u],
+                                         djz = tl.jz[t] - jzi[u];
                             const double gamma = (3.0 * (dvx * dax + dvy * day + dvz * daz) +
                                                   dxd * djx + dyd * djy + dzd * djz) * rinv2 +
                                                  alpha * (3.0 * beta - 4.0 * alpha * alpha);

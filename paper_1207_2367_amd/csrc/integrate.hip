@@ -752,9 +752,15 @@ constexpr uint32_t LOOP_SPINS = 1u << 21;                 // barrier wait bound 
 // launch; the host clears the words before it.  nblk <= TPB.
 constexpr int LOOP_FLAG = 32;   // uint32 words per flag line
 static_assert(LOOP_GRID <= TPB, "the barrier polls one flag per lane");
-__device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t *err,
-                                          uint32_t &epoch)
+// Barrier over the workgroups [f, f + W) (W <= TPB) as described above; a
+// group of one workgroup needs only the workgroup barrier.
+__device__ __forceinline__ bool group_sync(uint32_t *bar, uint32_t f, uint32_t W, uint32_t *err,
+                                           uint32_t &epoch)
 {
+    if (W == 1) {
+        __syncthreads();
+        return true;
+    }
     __shared__ int ok;
     const uint32_t e = ++epoch;
     if (threadIdx.x == 0)
@@ -765,9 +771,9 @@ __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t
         __hip_atomic_store(&bar[LOOP_FLAG * blockIdx.x], e, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (threadIdx.x < nblk) {
+    if (threadIdx.x < W) {
         uint32_t spins = 0;
-        while ((int32_t)(__hip_atomic_load(&bar[LOOP_FLAG * threadIdx.x], __ATOMIC_RELAXED,
+        while ((int32_t)(__hip_atomic_load(&bar[LOOP_FLAG * (f + threadIdx.x)], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT) - e) < 0) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > LOOP_SPINS) {
@@ -780,6 +786,12 @@ __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t
     }
     __syncthreads();
     return ok != 0;
+}
+
+__device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t nblk, uint32_t *err,
+                                          uint32_t &epoch)
+{
+    return group_sync(bar, 0, nblk, err, epoch);
 }
 
 // minimum of t + dt over [b, e) (ordered bits) and how many reach it; the
@@ -990,6 +1002,184 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
         res[3] = reason;
         res[4] = stop_n;
         __hip_atomic_store(&res[7], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// --------------------------------------------------- ensemble block steps
+// Independent clusters advanced to t_target in one persistent launch: the
+// workgroups form groups (EnsPlan: group g holds the W_g consecutive
+// workgroups from first[g] and integrates the clusters cl[cl_off[g] ..
+// cl_off[g+1]) one after another).  For each cluster the group runs the
+// block steps of step_loop_kernel restricted to the cluster's particles,
+// with its barriers restricted to the group (a group of one workgroup needs
+// only workgroup barriers), its active list at act[o0 ..) and its split
+// partials in the group's own part region [part_off[g], + part_cap[g])
+// slots.  Clusters never interact, so no barrier spans the chip.  The
+// evaluation shape follows N_act and the group size (1, 8 or 32 lanes per
+// particle, then source splits while the units do not yet give every
+// workgroup of the group two).  Per-workgroup minima and counts are kept in two
+// banks by cluster parity: a workgroup that has finished a cluster may start
+// the next while a slower one still reads the last decision's values.
+template <int PREC, bool EPS0, int LPI>
+__device__ __forceinline__ void ens_units(const typename Smem<PREC>::R &J, const ForceWork &w,
+                                          double *part, int64_t n_act, double eps2, int64_t n_ib,
+                                          int64_t B, int r, int W)
+{
+    const ForceOut none{};
+    for (int64_t u = r; u < n_ib * B; u += W)
+        force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
+                                                      (int)(u / n_ib));
+}
+
+// res (device): [0] sum of N_act, [1] sum of N_act * N_c, [2] largest number
+// of block steps of a cluster (the number of batched block steps of the
+// host-sized path)
+template <int PREC, bool EPS0>
+__global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
+    State st, JRecMixed jm, JRecPair32 jp, JRecF64 jd, int prec, int64_t n, double eps2,
+    double t_target, double eta, double dt_min, double dt_max, int32_t *act, double *part,
+    const int64_t *off, EnsPlan plan, uint64_t *wmin, int32_t *wcnt, uint32_t *bar,
+    uint32_t *err, int64_t *hist, unsigned long long *res)
+{
+    __shared__ double sum[9][RC_SLOTS];
+    const auto &J = loop_records<PREC>(jm, jp, jd);
+    const int g = plan.grp_of[blockIdx.x];
+    const uint32_t f = (uint32_t)plan.first[g], W = (uint32_t)plan.size[g];
+    const int r = (int)(blockIdx.x - f);
+    int64_t *seg = plan.seg + 2 * g;
+    double *gpart = part + plan.part_off[g] * 10;
+    const int64_t cap = plan.part_cap[g];
+    uint32_t epoch = 0;
+    int64_t act_sum = 0, pairs = 0, steps_max = 0;
+    bool failed = false;
+    for (int q = plan.cl_off[g]; q < plan.cl_off[g + 1] && !failed; ++q) {
+        const int c = plan.cl[q];
+        const int64_t o0 = off[c], o1 = off[c + 1], nc_ = o1 - o0;
+        const int64_t P = (nc_ + W - 1) / W;
+        const int64_t r0 = o0 + ((int64_t)r * P < nc_ ? (int64_t)r * P : nc_);
+        const int64_t r1 = r0 + P < o1 ? r0 + P : o1;
+        int32_t *act_c = act + o0;
+        uint64_t *wm = wmin + (q & 1) * LOOP_GMAX;
+        int32_t *wc = wcnt + (q & 1) * LOOP_GMAX;
+        int64_t steps = 0;
+        uint64_t v;
+        int cnt;
+        range_min_count(st.t, st.dt, r0, r1, v, cnt);
+        if (threadIdx.x == 0) {
+            wm[blockIdx.x] = v;
+            wc[blockIdx.x] = cnt;
+        }
+        for (;;) {
+            if (!group_sync(bar, f, W, err, epoch)) {
+                failed = true;
+                break;
+            }
+            // (2) block time, N_act and this workgroup's offset, alike in the group
+            uint64_t tv = ~0ull;
+            for (uint32_t k = threadIdx.x; k < W; k += TPB) {
+                const uint64_t x = wm[f + k];
+                tv = x < tv ? x : tv;
+            }
+            const uint64_t T_bits = block_min_u64(tv);
+            int64_t tot = 0, before = 0;
+            for (uint32_t k = threadIdx.x; k < W; k += TPB)
+                if (wm[f + k] == T_bits) {
+                    tot += wc[f + k];
+                    before += (int)k < r ? wc[f + k] : 0;
+                }
+            const int64_t n_act = block_sum_i64(tot);
+            const int64_t first = block_sum_i64(before);
+            const double T = __longlong_as_double((long long)T_bits);
+            if (*(volatile uint32_t *)err != 0) {
+                failed = true;
+                break;
+            }
+            if (n_act == 0 || !(T <= t_target))
+                break;
+            const int64_t mine = wm[blockIdx.x] == T_bits ? (int64_t)wc[blockIdx.x] : 0;
+            if (mine > 0)
+                scatter_range(st.t, st.dt, T, r0, r1, first, act_c);
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += TPB)
+                pack_h(st, jm, jp, jd, prec, n, i, T - st.t[i]);
+            if (r == 0 && threadIdx.x == 0) {
+                seg[0] = 0;
+                seg[1] = n_act;
+                int bb = 0;
+                while ((int64_t(1) << (bb + 1)) <= n_act)
+                    ++bb;
+                atomicAdd((unsigned long long *)&hist[bb], 1ull);
+            }
+            ++steps;
+            act_sum += n_act;
+            pairs += n_act * nc_;
+            if (!group_sync(bar, f, W, err, epoch)) {
+                failed = true;
+                break;
+            }
+            // (3) evaluation units of the group: i-blocks against source
+            // splits; lanes per particle so that the active particles fill
+            // the group's lanes (1, 8 or 32 lanes each)
+            const int64_t need = ((int64_t)TPB * W + n_act - 1) / n_act;
+            const int lpi = need <= 1 ? 1 : (need <= 8 ? 8 : 32);
+            const int64_t ib = (int64_t)LOOP_NW * (64 / lpi);
+            const int64_t n_ib = (n_act + ib - 1) / ib;
+            int64_t B = 1;
+            while (B * 2 <= LOOP_BMAX && B * 2 * n_ib <= 2 * (int64_t)W &&
+                   B * 2 * LOOP_NT <= nc_ && B * 2 * n_act <= cap)
+                B *= 2;
+            ForceWork w{};
+            w.idx = act_c;
+            w.seg = seg;
+            w.off = off + c;
+            w.split = (int32_t)B;
+            w.nc = 1;
+            w.n_blocks = n_ib;
+            if (lpi == 32)
+                ens_units<PREC, EPS0, 32>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+            else if (lpi == 8)
+                ens_units<PREC, EPS0, 8>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+            else
+                ens_units<PREC, EPS0, 1>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+            if (!group_sync(bar, f, W, err, epoch)) {
+                failed = true;
+                break;
+            }
+            // (4) this workgroup's active particles: split sums (fixed order)
+            // and the corrector, RC_SLOTS particles per pass
+            const int64_t bc = splits_used(nc_, B, LOOP_NT);
+            const int qq = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
+            for (int64_t k0 = first; k0 < first + mine; k0 += RC_SLOTS) {
+                const int64_t k = k0 + kl;
+                const bool in = k < first + mine;
+                const bool corr = threadIdx.x < RC_SLOTS && in;
+                OldState o{};
+                if (corr)
+                    o = load_old(st, n, act_c[k]);
+                if (qq < 9 && in)
+                    sum[qq][kl] = sum_splits(gpart + (int64_t)qq * n_act + k, 10 * n_act, bc);
+                __syncthreads();
+                if (corr) {
+                    const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
+                    const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
+                    const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
+                    correct_loaded(st, n, act_c[k], o, a1, j1, s1, t_target, eta, dt_min,
+                                   dt_max, err);
+                }
+                __syncthreads();
+            }
+            // (1) of the next step, over the range this workgroup just updated
+            range_min_count(st.t, st.dt, r0, r1, v, cnt);
+            if (threadIdx.x == 0) {
+                wm[blockIdx.x] = v;
+                wc[blockIdx.x] = cnt;
+            }
+        }
+        steps_max = steps > steps_max ? steps : steps_max;
+    }
+    if (r == 0 && threadIdx.x == 0) {
+        atomicAdd(&res[0], (unsigned long long)act_sum);
+        atomicAdd(&res[1], (unsigned long long)pairs);
+        atomicMax(&res[2], (unsigned long long)steps_max);
     }
 }
 
@@ -1284,7 +1474,69 @@ const void *step_loop_fn(const Ctx &c)
     }
 }
 
+// the ensemble loop kernel for a context's precision and softening
+const void *ensemble_loop_fn(const Ctx &c)
+{
+    const bool e0 = c.eps == 0.0;
+    switch (c.cfg.precision) {
+    case NBODY_PREC_FP64:
+        return e0 ? (const void *)ensemble_loop_kernel<PREC_F64, true>
+                  : (const void *)ensemble_loop_kernel<PREC_F64, false>;
+    case NBODY_PREC_FP32PAIR:
+        return e0 ? (const void *)ensemble_loop_kernel<PREC_PAIR32, true>
+                  : (const void *)ensemble_loop_kernel<PREC_PAIR32, false>;
+    default:
+        return e0 ? (const void *)ensemble_loop_kernel<PREC_MIXED, true>
+                  : (const void *)ensemble_loop_kernel<PREC_MIXED, false>;
+    }
+}
+
 }  // namespace
+
+int ensemble_max_grid(const Ctx &c)
+{
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ensemble_loop_fn(c), TPB, 0) !=
+            hipSuccess)
+        return 0;
+    if (!coop || per_cu < 1 || cus < 1)
+        return 0;
+    const int64_t g = (int64_t)per_cu * cus;
+    return g < LOOP_GMAX ? (int)g : LOOP_GMAX;
+}
+
+// The ensemble's block steps to t_target in one launch (see
+// ensemble_loop_kernel).  The caller has reset the barrier words and res,
+// and filled the plan's tables; grid <= ensemble_max_grid(c).
+hipError_t launch_ensemble_loop(const Ctx &c, double t_target, int grid, const EnsPlan &plan,
+                                unsigned long long *res, hipStream_t s)
+{
+    State st = c.st;
+    JRecMixed jm = c.jm;
+    JRecPair32 jp = c.jp;
+    JRecF64 jd = c.jd;
+    int prec = c.cfg.precision;
+    int64_t n = c.n;
+    double eps2 = c.eps * c.eps, tt = t_target, eta = c.cfg.eta, dmin = c.cfg.dt_min,
+           dmax = c.cfg.dt_max;
+    int32_t *act = c.act;
+    double *part = c.part;
+    const int64_t *off = c.d_off;
+    EnsPlan pl = plan;
+    uint64_t *wmin = c.d_loop_min;
+    int32_t *wcnt = c.d_loop_cnt;
+    uint32_t *bar = c.d_loop_bar;
+    uint32_t *err = c.d_err;
+    int64_t *hist = c.d_info + 8;
+    unsigned long long *r = res;
+    void *args[] = {&st,  &jm,   &jp,  &jd,  &prec, &n,    &eps2, &tt,  &eta, &dmin,
+                    &dmax, &act, &part, &off, &pl,   &wmin, &wcnt, &bar, &err, &hist, &r};
+    return hipLaunchCooperativeKernel(ensemble_loop_fn(c), dim3((unsigned)grid), dim3(TPB), args,
+                                      0, s);
+}
 
 int step_loop_max_grid(const Ctx &c)
 {

@@ -73,6 +73,22 @@ struct ForceWork {
 // Launch shape of the evaluation: lanes per active particle, waves per
 // workgroup, split-source factor, active particles per lane group (1 or 2;
 // 2 only with lpi <= 4).
+// Work split of the ensemble loop (independent clusters in one persistent
+// launch): group g holds the size[g] consecutive workgroups from first[g]
+// and integrates the clusters cl[cl_off[g] .. cl_off[g+1]) one after
+// another, with its split partials in slots [part_off[g], + part_cap[g]).
+// Device arrays in the workspace.
+struct EnsPlan {
+    const int32_t *grp_of;     // [G] group of each workgroup
+    const int32_t *first;      // [ng] first workgroup of the group
+    const int32_t *size;       // [ng] workgroups of the group
+    const int32_t *cl;         // [nc] clusters, group after group
+    const int32_t *cl_off;     // [ng + 1]
+    const int64_t *part_off;   // [ng]
+    const int64_t *part_cap;   // [ng]
+    int64_t *seg;              // [2 ng] active segment of the group's cluster
+};
+
 struct Launch {
     int lpi = 0, waves = 0, split = 0, ipt = 1;
 };
@@ -129,6 +145,10 @@ hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int gr
 // workgroups of the device-resident loop that can be resident at once for
 // the context's precision (0 if the device cannot launch it cooperatively)
 int step_loop_max_grid(const Ctx &c);
+// the same for the ensemble loop (every resident workgroup, <= LOOP_GMAX)
+int ensemble_max_grid(const Ctx &c);
+hipError_t launch_ensemble_loop(const Ctx &c, double t_target, int grid, const EnsPlan &plan,
+                                unsigned long long *res, hipStream_t s);
 hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
 hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
@@ -159,6 +179,9 @@ constexpr int LOOP_GMAX = 1024;
 constexpr int LOOP_GRID = 64;            // workgroups the loop uses
 constexpr int64_t LOOP_AUTO_NMAX = 8192; // automatic mode: systems up to this size
 constexpr int64_t LOOP_BAR_WORDS = 32 * LOOP_GMAX;         // one flag line per workgroup
+// largest group of the ensemble loop (its barrier polls one flag per lane of
+// a 256-lane workgroup)
+constexpr int ENS_GROUP_MAX = 256;
 
 // Schedule scratch: chunk table built at init (a chunk never spans two
 // clusters), per-cluster block times and active segments.
@@ -219,8 +242,15 @@ struct Ctx {
     int64_t loop_seq = 0;                // same for the device-resident loop (h_tot[15])
     int64_t loop_amax = -1;              // loop's largest N_act: -1 automatic, 0 off
     int loop_grid = -1;                  // its workgroups (-1: not yet queried, 0: none)
-    uint64_t *d_loop_min = nullptr;      // [LOOP_GMAX] per-workgroup minima
-    int32_t *d_loop_cnt = nullptr;       // [LOOP_GMAX] and counts
+    uint64_t *d_loop_min = nullptr;      // [2 LOOP_GMAX] per-workgroup minima (two banks)
+    int32_t *d_loop_cnt = nullptr;       // [2 LOOP_GMAX] and counts
+    // ensemble loop: plan tables (device, in the workspace), its grid (-1
+    // not yet planned, 0 unavailable), and its result counters
+    EnsPlan ens{};
+    int32_t *d_ens_i32 = nullptr;        // grp_of, first, size, cl_off, cl
+    int64_t *d_ens_i64 = nullptr;        // part_off, part_cap, seg
+    int ens_grid = -1;
+    unsigned long long *d_ens_res = nullptr;   // [4]
     uint32_t *d_loop_bar = nullptr;      // [LOOP_BAR_WORDS] grid barrier words
     int64_t *d_tot = nullptr;            // device address of h_tot
     double *h_red = nullptr;

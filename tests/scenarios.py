@@ -12,6 +12,7 @@ benchmark).  Test infrastructure: not collected by pytest, run by hand:
     python tests/scenarios.py etascan        # energy error against eta
     python tests/scenarios.py etascan:32768:mixed   # one size, one path
     python tests/scenarios.py blocks32k      # where a small-block run spends its time
+    python tests/scenarios.py plummer_to64:2097152   # 8M configuration's steps, 2M bodies
 """
 from __future__ import annotations
 
@@ -503,9 +504,43 @@ def blocks32k(n=32768, t_end=1.0):
             "evaluation_by_log2_n_act": _by_log2(na_log, pr_log, ms_log)}
 
 
+def plummer_to64(n=1 << 21, t_end=1.0 / 64):
+    """The 8M-body configuration's integration at a size that fits one run
+    (seed 5005, eps 1e-4, eta 0.45): one FP64 start-up, its state copied
+    into a mixed context, then both paths to t = 1/64 (the target caps the
+    last steps); energy error, block-level N_act histogram (log2 bins and
+    the paper's Fig. 7 groups), interactions and rates."""
+    import ics
+    from paper_1207_2367_amd import PREC_FP64, PREC_MIXED, System
+    n = int(n)
+    t_end = float(t_end)
+    m, x, v = ics.plummer(n, 5005)
+    res = {"config": "plummer_to64", "n": n, "t_end": t_end}
+    t0 = time.perf_counter()
+    f = System(m, x, v, 1e-4, precision=PREC_FP64)
+    torch.cuda.synchronize()
+    res["startup_s"] = time.perf_counter() - t0
+    _log(f"  start-up of {n} bodies: {res['startup_s']:.1f} s")
+    st0 = f.get_state()
+    g = System(m, x, v, 1e-4, precision=PREC_MIXED, skip_startup=True)
+    g.set_state(**st0)
+    e0 = sum(f.energy()[:2])
+    for name, s in (("mixed", g), ("fp64", f)):
+        st, wall, _ = _run(s, t_end, profile=False, pieces=4)
+        e1 = sum(s.energy()[:2])
+        res[name] = {"dE_over_E": (e1 - e0) / e0, "block_steps": st["block_steps"],
+                     "interactions": st["interactions"], "wall_s": wall,
+                     "G_interactions_per_s": st["interactions"] / wall / 1e9,
+                     "hist_log2": st["hist"], "groups": _hist_groups(st["hist"])}
+        _log(f"  {name}: {res[name]['block_steps']} block steps, dE/E {res[name]['dE_over_E']:.3e}")
+        s.close()
+    return res
+
+
 RUNS = {"plummer1k": plummer1k, "force64k": force64k, "plummer1m": plummer1m,
         "king256": king256, "plummer8m": plummer8m, "bfactor16k": bfactor16k,
-        "etascan": etascan, "blocks32k": blocks32k, "bh64k": bh64k, "ensemble": ensemble}
+        "etascan": etascan, "blocks32k": blocks32k, "bh64k": bh64k, "ensemble": ensemble,
+        "plummer_to64": plummer_to64}
 
 
 def _default(o):
