@@ -502,14 +502,25 @@ int wait_words(Ctx &c, int first, int count, int seq_word, int64_t seq, int64_t 
 
 int wait_totals(Ctx &c, int64_t seq, int64_t tot[6]) { return wait_words(c, 0, 6, 6, seq, tot); }
 
-// Work split of the ensemble loop over G workgroups: a cluster whose share
-// of the estimated work (N_c^2) is at least two workgroups' worth gets a
-// group of its own, the largest power of two of workgroups within its
-// share (at most ENS_GROUP_MAX); the other clusters go to single-workgroup groups,
-// largest first onto the least loaded (longest-processing-time packing).
-// Each group's partial slots are twice its largest cluster, so the groups'
-// regions fit the split buffer (2 n slots).  Copies the tables to the
-// device and sets c.ens; returns the number of workgroups to launch.
+// Work split of the ensemble loop over G workgroups.  Cost model, in units
+// of N^2 (pair evaluations per block step scale with N_c^2): a cluster on W
+// workgroups costs N_c^2 / W + L_W, where L_W stands for the latency of its
+// block steps (thousands of steps of a few barriers and memory round trips
+// each, about the same count for every cluster of a King ensemble);
+// measured on the 256-cluster King W0 = 6 ensemble on the MI355X: a
+// one-workgroup cluster of 256 bodies takes as long as 6e5 N^2 units
+// (~775^2), a multi-workgroup group about twice that.  The plan is the
+// smallest makespan M (bisection) for which: a cluster with N_c^2 + L_1 > M
+// gets a group of its own of ceil(N_c^2 / (M - L_W)) workgroups (at most
+// ENS_GROUP_MAX), and the others are packed first-fit-decreasing onto
+// single-workgroup groups of capacity M.  Workgroups left over go to the
+// groups with the most work per workgroup.  A group integrates its clusters
+// one after another.  Each group's partial slots are twice its largest
+// cluster, so the groups' regions fit the split buffer (2 n slots).  Copies
+// the tables to the device and sets c.ens; returns the number of workgroups
+// to launch.
+constexpr double ENS_LAT_ONE = 6.0e5, ENS_LAT_GROUP = 1.2e6;
+
 int plan_ensemble(Ctx &c, int G)
 {
     const int nc = c.nc;
@@ -524,38 +535,78 @@ int plan_ensemble(Ctx &c, int G)
     double total = 0.0;
     for (int k = 0; k < nc; ++k)
         total += work(k);
-    std::vector<std::vector<int>> groups;   // clusters of each group
+    // groups for a makespan M: {clusters}, workgroups, work; false if they
+    // need more than G workgroups or a cluster cannot finish within M
+    std::vector<std::vector<int>> groups;
     std::vector<int> gsize;
+    std::vector<double> gwork;
+    auto build = [&](double M) {
+        groups.clear();
+        gsize.clear();
+        gwork.clear();
+        int used = 0;
+        size_t q = 0;
+        for (; q < order.size() && work(order[q]) + ENS_LAT_ONE > M; ++q) {
+            const double w = work(order[q]);
+            if (M <= ENS_LAT_GROUP)
+                return false;
+            const int W = (int)std::min<double>(std::ceil(w / (M - ENS_LAT_GROUP)),
+                                                ENS_GROUP_MAX);
+            if (w / W + ENS_LAT_GROUP > M * (1 + 1e-12))
+                return false;
+            groups.push_back({order[q]});
+            gsize.push_back(W);
+            gwork.push_back(w);
+            used += W;
+        }
+        const size_t first_bin = groups.size();
+        for (; q < order.size(); ++q) {
+            const double w = work(order[q]) + ENS_LAT_ONE;
+            size_t b = first_bin;
+            while (b < groups.size() && gwork[b] + w > M * (1 + 1e-12))
+                ++b;
+            if (b == groups.size()) {
+                groups.push_back({});
+                gsize.push_back(1);
+                gwork.push_back(0.0);
+                ++used;
+            }
+            groups[b].push_back(order[q]);
+            gwork[b] += w;
+        }
+        return used <= G;
+    };
+    double lo = total / G, hi = total + nc * (ENS_LAT_ONE + ENS_LAT_GROUP) + 1.0;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (build(mid))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    if (!build(hi))
+        return 0;
     int used = 0;
-    size_t nbig = 0;
-    for (; nbig < order.size(); ++nbig) {
-        const double share = total > 0.0 ? work(order[nbig]) / total * G : 0.0;
-        int W = 1;
-        while (W * 2 <= share && W * 2 <= ENS_GROUP_MAX)
-            W *= 2;
-        // keep at least one workgroup for every cluster not yet placed
-        const int rest = (int)std::min<size_t>(order.size() - nbig - 1, (size_t)G);
-        while (W > 1 && used + W + (rest > 0 ? 1 : 0) > G)
-            W /= 2;
-        if (W < 2)
-            break;
-        groups.push_back({order[nbig]});
-        gsize.push_back(W);
+    for (int W : gsize)
         used += W;
-    }
-    const int nsingle = std::min<int>(G - used, (int)(order.size() - nbig));
-    std::vector<double> load(nsingle, 0.0);
-    const size_t g0 = groups.size();
-    for (int k = 0; k < nsingle; ++k) {
-        groups.push_back({});
-        gsize.push_back(1);
-    }
-    for (size_t q = nbig; q < order.size(); ++q) {
-        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        groups[g0 + b].push_back(order[q]);
-        load[b] += work(order[q]);
+    // spare workgroups to the groups with the most work per workgroup
+    // (groups of one cluster only, so that a group's clusters keep sharing
+    // one slice plan)
+    for (; used < G; ++used) {
+        int best = -1;
+        double bw = 0.0;
+        for (size_t g = 0; g < groups.size(); ++g)
+            if (groups[g].size() == 1 && gsize[g] < ENS_GROUP_MAX && gwork[g] / gsize[g] > bw) {
+                bw = gwork[g] / gsize[g];
+                best = (int)g;
+            }
+        if (best < 0)
+            break;
+        ++gsize[best];
     }
     const int ng = (int)groups.size();
+    if (ng > LOOP_GMAX)
+        return 0;
     std::vector<int32_t> i32(4 * LOOP_GMAX + 1 + nc, 0);
     std::vector<int64_t> i64(4 * LOOP_GMAX, 0);
     int32_t *grp_of = i32.data(), *first = grp_of + LOOP_GMAX, *size = first + LOOP_GMAX;
@@ -579,7 +630,7 @@ int plan_ensemble(Ctx &c, int G)
         slot += 2 * big;
     }
     cl_off[ng] = ncl;
-    if (slot > c.part_cap || ncl != nc)
+    if (slot > c.part_cap || ncl != nc || wg > G)
         return 0;
     if (hipMemcpyAsync(c.d_ens_i32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice,
                        c.stream) != hipSuccess ||

@@ -1016,8 +1016,8 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
 // partials in the group's own part region [part_off[g], + part_cap[g])
 // slots.  Clusters never interact, so no barrier spans the chip.  The
 // evaluation shape follows N_act and the group size (1, 8 or 32 lanes per
-// particle, then source splits while the units do not yet give every
-// workgroup of the group two).  Per-workgroup minima and counts are kept in two
+// particle, then source splits, for about four units per workgroup of a
+// group).  Per-workgroup minima and counts are kept in two
 // banks by cluster parity: a workgroup that has finished a cluster may start
 // the next while a slower one still reads the last decision's values.
 template <int PREC, bool EPS0, int LPI>
@@ -1117,15 +1117,19 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
                 break;
             }
             // (3) evaluation units of the group: i-blocks against source
-            // splits; lanes per particle so that the active particles fill
-            // the group's lanes (1, 8 or 32 lanes each)
-            const int64_t need = ((int64_t)TPB * W + n_act - 1) / n_act;
+            // splits.  One workgroup takes the block in as few units as its
+            // lanes allow; a group of several wants about four units per
+            // workgroup, so that units of unequal length still balance:
+            // lanes per particle (1, 8 or 32) for that many lanes, then
+            // source splits for that many units.
+            const int64_t units = W == 1 ? 1 : 4 * (int64_t)W;
+            const int64_t need = ((int64_t)TPB * units + n_act - 1) / n_act;
             const int lpi = need <= 1 ? 1 : (need <= 8 ? 8 : 32);
             const int64_t ib = (int64_t)LOOP_NW * (64 / lpi);
             const int64_t n_ib = (n_act + ib - 1) / ib;
             int64_t B = 1;
-            while (B * 2 <= LOOP_BMAX && B * 2 * n_ib <= 2 * (int64_t)W &&
-                   B * 2 * LOOP_NT <= nc_ && B * 2 * n_act <= cap)
+            while (B * 2 <= LOOP_BMAX && B * n_ib < units && B * 2 * LOOP_NT <= nc_ &&
+                   B * 2 * n_act <= cap)
                 B *= 2;
             ForceWork w{};
             w.idx = act_c;

@@ -233,10 +233,11 @@ class System:
             load().nbody_free(self.ctx)
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down (the runtime's own
-        # teardown may already be under way): close() systems explicitly
-        if sys.is_finalizing():
+        # teardown may already be under way, and module globals may already
+        # be cleared): close() systems explicitly
+        if _finalizing():
             return
         try:
             self.close()
