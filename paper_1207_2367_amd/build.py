@@ -52,12 +52,14 @@ def build(verbose: bool = True) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
-    # VALU throughput / v_rsq_f32 rounding probe (a stand-alone executable)
-    probe = os.path.join(HERE, "valu_probe")
-    subprocess.check_call(["hipcc", *[f for f in FLAGS if f != "-fPIC"], "-o", probe + ".tmp",
-                           os.path.join(CSRC, "valu_probe.hip")],
-                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
-    os.replace(probe + ".tmp", probe)
+    # stand-alone probes: VALU throughput / v_rsq_f32 rounding, and the cost
+    # of a barrier across the workgroups of a cooperative launch
+    for name in ("valu_probe", "barrier_probe"):
+        probe = os.path.join(HERE, name)
+        subprocess.check_call(["hipcc", *[f for f in FLAGS if f != "-fPIC"], "-o",
+                               probe + ".tmp", os.path.join(CSRC, name + ".hip")],
+                              stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+        os.replace(probe + ".tmp", probe)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s")
     return LIB

@@ -739,21 +739,23 @@ constexpr int LOOP_NT = LOOP_NW * 64;                     // sources per tile
 constexpr int LOOP_BMAX = 64;                             // largest split
 constexpr uint32_t LOOP_SPINS = 1u << 21;                 // barrier wait bound (~2 s)
 
-// Grid barrier with one flag word per workgroup (bar[LOOP_FLAG * w], a
-// 128-byte line each): every workgroup releases its writes (device-scope
-// fence), stores the barrier's epoch into its flag, then polls all nblk flags
-// at once (one lane per flag) until each holds this epoch or a later one (a
-// workgroup that already passed stores the next epoch), and fences once to
-// acquire the others' writes.  One store-to-poll hop per barrier, polls are
-// relaxed loads (no cache invalidation per poll) and no word has more than
-// one writer.  A wait longer than LOOP_SPINS polls sets ERR_LOOP and returns
-// false (the workgroup then leaves the loop; the others follow at their
-// next barrier), so no wave can wait forever.  Epochs start at 1 in every
-// launch; the host clears the words before it.  nblk <= TPB.
-constexpr int LOOP_FLAG = 32;   // uint32 words per flag line
-static_assert(LOOP_GRID <= TPB, "the barrier polls one flag per lane");
-// Barrier over the workgroups [f, f + W) (W <= TPB) as described above; a
-// group of one workgroup needs only the workgroup barrier.
+// Barrier over the workgroups [f, f + W) of a cooperative launch: one
+// arrival counter (bar[LOOP_FLAG * f], monotonic within a launch) and one
+// generation word (bar[LOOP_FLAG * (f + 1)], its own 128-byte line).  Each
+// workgroup releases its writes (agent-scope release fence) and adds 1 to the
+// counter; the arrival that brings it to e W (epoch e, uint32 arithmetic,
+// so it wraps consistently) acquires the others' writes and stores e into
+// the generation word with release order; the others poll that word and
+// acquire once it holds e or later.  One release and one acquire per
+// workgroup and barrier: the fences (which write back / invalidate the
+// XCD's L2) are what a barrier costs here, about 1.1 us at W = 16 and growing
+// with W (measured: 3.3 us at W = 64, 11 us at 256, against 6.9 and 26 us
+// for one flag per workgroup polled by every workgroup with two full fences
+// each).  A wait longer than LOOP_SPINS polls sets ERR_LOOP and returns
+// false (the workgroup then leaves the loop; the others follow at their next
+// barrier), so no wave waits forever.  Epochs start at 1 in every launch;
+// the host clears the words before it.
+constexpr int LOOP_FLAG = 32;   // uint32 words per line
 __device__ __forceinline__ bool group_sync(uint32_t *bar, uint32_t f, uint32_t W, uint32_t *err,
                                            uint32_t &epoch)
 {
@@ -763,26 +765,29 @@ __device__ __forceinline__ bool group_sync(uint32_t *bar, uint32_t f, uint32_t W
     }
     __shared__ int ok;
     const uint32_t e = ++epoch;
-    if (threadIdx.x == 0)
-        ok = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_store(&bar[LOOP_FLAG * blockIdx.x], e, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x < W) {
-        uint32_t spins = 0;
-        while ((int32_t)(__hip_atomic_load(&bar[LOOP_FLAG * (f + threadIdx.x)], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT) - e) < 0) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > LOOP_SPINS) {
-                atomicOr(err, ERR_LOOP);
-                ok = 0;
-                break;
+        ok = 1;
+        uint32_t *cnt = bar + LOOP_FLAG * f, *gen = bar + LOOP_FLAG * (f + 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old == e * W - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(gen, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while ((int32_t)(__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                             e) < 0) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > LOOP_SPINS) {
+                    atomicOr(err, ERR_LOOP);
+                    ok = 0;
+                    break;
+                }
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return ok != 0;

@@ -178,9 +178,9 @@ enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
 constexpr int LOOP_GMAX = 1024;
 constexpr int LOOP_GRID = 64;            // workgroups the loop uses
 constexpr int64_t LOOP_AUTO_NMAX = 8192; // automatic mode: systems up to this size
-constexpr int64_t LOOP_BAR_WORDS = 32 * LOOP_GMAX;         // one flag line per workgroup
-// largest group of the ensemble loop (its barrier polls one flag per lane of
-// a 256-lane workgroup)
+constexpr int64_t LOOP_BAR_WORDS = 32 * LOOP_GMAX;         // barrier lines (128 B each)
+// largest group of the ensemble loop (a barrier's cost grows with the
+// group's size: beyond 256 workgroups it outweighs the extra lanes)
 constexpr int ENS_GROUP_MAX = 256;
 
 // Schedule scratch: chunk table built at init (a chunk never spans two
