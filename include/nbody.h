@@ -47,7 +47,11 @@ extern "C" {
      FP64; the snap terms in FP32 with compensated (double-single)
      accumulation.  Acceleration, jerk and potential are within 1e-6
      (relative, per particle) of an FP64 evaluation; the snap within about
-     1e-6 times the condition number of its sum.  The step criterion's
+     1e-6 times the condition number of its sum.  Energy conservation over
+     many block steps matches the FP64 mode's (|dE/E| within 2x, measured
+     on Plummer spheres of 2^15 and 2^16 bodies) for eta <= 0.8; at eta = 1
+     the criterion no longer resolves close encounters in either mode and
+     the two runs differ by up to ~3x.  The step criterion's
      fifth-derivative estimate amplifies the acceleration's absolute error
      by ~720/h^5, which with FP32 acceleration terms can drive steps down
      to dt_min.
@@ -292,6 +296,23 @@ int nbody_set_tuning(nbody_ctx *ctx, const nbody_launch *table, int32_t count);
    waits for more than about two seconds ends the launch with
    NBODY_EDEVICE instead of hanging.  Returns NBODY_EINVAL for a NULL ctx. */
 int nbody_set_step_loop(nbody_ctx *ctx, int64_t max_active);
+
+/* How nbody_step finds the next block of a single system on the host-sized
+   path (the block-step scheme of paper Sect. 2 and the active-set selection
+   of Table 1, section 1).  mode 0 (the default): from per-level counts --
+   the number of particles on each step dt_max 2^-k, kept up to date by the
+   corrector -- whenever the state allows it (every step a power of two in
+   [dt_min, dt_max], every particle at a multiple of its step and short of
+   its next one, which the integrator keeps; checked once per nbody_step
+   call): the next block time is the earliest next multiple of an occupied
+   level's step, its particles those of the levels whose step divides it, so
+   no sweep over all particles is needed; the active list is then filled in
+   chunk order of completion (the results do not depend on it).  mode 1: a
+   sweep of every particle's next time per block step (always used for
+   several clusters, by the device-resident loops and by nbody_schedule and
+   nbody_block_step).  Both give the same blocks.  Returns NBODY_EINVAL for
+   a NULL ctx or another mode. */
+int nbody_set_schedule(nbody_ctx *ctx, int mode);
 
 /* GPU time per phase of the block step, measured with HIP events on the
    context's stream while profiling is on (phases follow the paper's

@@ -116,6 +116,8 @@ int take_err(Ctx &c)
         return fail(c, NBODY_EDEVICE, "a grid barrier of the device-resident loop timed out");
     if (e & ERR_STATE)
         return fail(c, NBODY_ESTATE, "the particles of a cluster are not at one time");
+    if (e & ERR_LEVELS)
+        return fail(c, NBODY_EDEVICE, "the schedule from level counts and the active list disagree");
     return fail(c, NBODY_EINVAL, "index list out of range / not ascending, or a particle is past the target time");
 }
 
@@ -243,6 +245,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     int32_t *blk_cl = (int32_t *)take((n + nc + 1) * 4);
     int64_t *blk_first = (int64_t *)take((nc + 1) * 8);
     int64_t *info = (int64_t *)take(64 * 8);
+    int64_t *lvl = (int64_t *)take(LVL_WORDS * 8);
     uint64_t *loop_min = (uint64_t *)take(2 * LOOP_GMAX * 8);
     int32_t *loop_cnt = (int32_t *)take(2 * LOOP_GMAX * 4);
     // ensemble plan: grp_of, first, size [LOOP_GMAX each], cl_off [LOOP_GMAX + 1],
@@ -277,6 +280,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
         c->d_blk_cluster = blk_cl;
         c->d_blk_first = blk_first;
         c->d_info = info;
+        c->d_lvl = lvl;
         c->d_loop_min = loop_min;
         c->d_loop_cnt = loop_cnt;
         c->d_ens_i32 = ens_i32;
@@ -742,9 +746,33 @@ int run_loop(Ctx &c, double t_target, nbody_step_stats *stats, int *reason)
     return NBODY_OK;
 }
 
-// one block step; fills n_act / t_block and adds to stats
+// Whether nbody_step schedules this context from per-level counts: one
+// system, not left to the device-resident loop, a level range that fits
+// LVL_N, and a state that meets the conditions (every step a power of two in
+// [dt_min, dt_max], every particle at a multiple of its step and short of its
+// next one); the counts are built here, once per call.
+int levels_ready(Ctx &c, bool *ok)
+{
+    *ok = false;
+    if (c.nc != 1 || c.sched_mode != 0)
+        return NBODY_OK;
+    const bool loop = c.loop_amax != 0 && c.pinned.lpi == 0 && !c.prof && c.loop_grid != 0 &&
+                      !(c.loop_amax < 0 && c.n > LOOP_AUTO_NMAX);
+    if (loop || std::ilogb(c.cfg.dt_max) - std::ilogb(c.cfg.dt_min) >= LVL_N)
+        return NBODY_OK;
+    HIPCHK(c, launch_levels_build(c, c.stream));
+    HIPCHK(c, hipMemcpyAsync(c.h_info, c.d_lvl + LVL_BAD, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    *ok = c.h_info[0] == 0;
+    return NBODY_OK;
+}
+
+// one block step; fills n_act / t_block and adds to stats.  levels: the
+// schedule comes from the per-level counts (levels_ready said so), which
+// the corrector keeps up to date
 int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
-               nbody_step_stats *stats)
+               nbody_step_stats *stats, bool levels)
 {
     // the host needs N_act (and the block time) to size the evaluation; it
     // waits for the scan's totals only (written into mapped host memory),
@@ -753,10 +781,13 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
     // when nothing is due)
     int rec = prof_begin(c, PH_SCHED);
     const int64_t seq = ++c.sched_seq;
-    HIPCHK(c, launch_sched_head(c, t_target, seq, c.stream));
+    if (levels)
+        HIPCHK(c, launch_levels_sched(c, t_target, seq, c.stream));
+    else
+        HIPCHK(c, launch_sched_head(c, t_target, seq, c.stream));
     prof_end(c, rec);
     rec = prof_begin(c, PH_PREDICT);   // the compaction of the active list runs here too
-    HIPCHK(c, launch_scatter_pack(c, c.stream));
+    HIPCHK(c, launch_scatter_pack(c, c.stream, levels));
     prof_end(c, rec);
     int64_t tot[6];
     if (int rc = wait_totals(c, seq, tot))
@@ -788,10 +819,11 @@ int block_step(Ctx &c, double t_target, int64_t *n_act_out, double *t_block_out,
         return rc;
     rec = prof_begin(c, PH_CORRECT);
     if (w.split > 1)
-        HIPCHK(c, launch_reduce_correct(c, w, w.split, 64 * L.waves, n_act, t_target, c.stream));
+        HIPCHK(c, launch_reduce_correct(c, w, w.split, 64 * L.waves, n_act, t_target, c.stream,
+                                        levels));
     else
         HIPCHK(c, launch_correct(c, n_act, c.act, t_target, out.vec[0], out.vec[1], out.vec[2], 1,
-                                 n_act, c.stream));
+                                 n_act, c.stream, levels));
     prof_end(c, rec);
     if (stats) {
         stats->block_steps += 1;
@@ -1068,7 +1100,7 @@ int nbody_block_step(nbody_ctx *ctx, double t_target, int64_t *n_act, double *t_
     Ctx &c = ctx->c;
     if (!n_act || !t_block || !on_grid(t_target, c.cfg.dt_min))
         return fail(c, NBODY_EINVAL, "bad argument");
-    int rc = block_step(c, t_target, n_act, t_block, nullptr);
+    int rc = block_step(c, t_target, n_act, t_block, nullptr, false);
     if (rc)
         return rc;
     return take_err(c);
@@ -1093,6 +1125,9 @@ int nbody_step(nbody_ctx *ctx, double t_target, nbody_step_stats *stats)
     rc = run_ensemble(c, t_target, stats, &done);
     if (rc)
         return rc;
+    bool levels = false;
+    if (!done && (rc = levels_ready(c, &levels)) != NBODY_OK)
+        return rc;
     for (; !done;) {
         // small blocks inside one launch; a larger one on the host path
         int reason = 0;
@@ -1103,7 +1138,7 @@ int nbody_step(nbody_ctx *ctx, double t_target, nbody_step_stats *stats)
             break;
         int64_t na = 0;
         double tb = 0.0;
-        rc = block_step(c, t_target, &na, &tb, stats);
+        rc = block_step(c, t_target, &na, &tb, stats, levels);
         if (rc)
             return rc;
         if (na == 0)
@@ -1248,6 +1283,14 @@ int nbody_set_step_loop(nbody_ctx *ctx, int64_t max_active)
     if (!ctx)
         return NBODY_EINVAL;
     ctx->c.loop_amax = max_active < 0 ? -1 : max_active;
+    return NBODY_OK;
+}
+
+int nbody_set_schedule(nbody_ctx *ctx, int mode)
+{
+    if (!ctx || (mode != 0 && mode != 1))
+        return NBODY_EINVAL;
+    ctx->c.sched_mode = mode;
     return NBODY_OK;
 }
 

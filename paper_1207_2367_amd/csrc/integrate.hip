@@ -29,6 +29,13 @@ __device__ __forceinline__ double pow2_floor(double x)
     return __longlong_as_double(__double_as_longlong(x) & (long long)0xFFF0000000000000ULL);
 }
 
+// Per-level counts (a schedule from levels): level of a power-of-two step,
+// dt = 2^(e0 - k) with e0 the exponent of dt_max.
+__device__ __forceinline__ int dt_level(double dt, int e0)
+{
+    return e0 - ((int)((__double_as_longlong(dt) >> 52) & 0x7FF) - 1023);
+}
+
 __device__ __forceinline__ double norm3(double x, double y, double z)
 {
     return sqrt(x * x + y * y + z * z);
@@ -167,6 +174,16 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     for (int m = 32; m >= 1; m >>= 1) {
         const uint64_t o = __shfl_xor(v, m, 64);
         v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = __shfl_xor(v, m, 64);
+        v = o > v ? o : v;
     }
     return v;
 }
@@ -429,6 +446,37 @@ __global__ __launch_bounds__(TPB) void sched_scatter(const double *t, const doub
 // workgroups compact one chunk each, the rest predict TPB sources each to
 // their cluster's block time.  Both read only the schedule's results and
 // the stored state; they write disjoint arrays.
+// With fill != nullptr (one system, schedule from levels) a chunk counts its
+// due particles, takes their place in the list with one atomic add on *fill
+// and writes them in ascending order there (chunks land in any order; the
+// evaluation and the corrector of a particle do not depend on its slot).
+__device__ __forceinline__ void scatter_chunk_fill(const double *t, const double *dt, double T,
+                                                   int64_t b, int64_t e, int32_t *act,
+                                                   int64_t *fill)
+{
+    __shared__ int wcnt[TPB / 64];
+    __shared__ int64_t base;
+    int mine = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += TPB)
+        mine += due(t[i], dt[i], T) ? 1 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        mine += __shfl_xor(mine, m, 64);
+    if ((threadIdx.x & 63) == 0)
+        wcnt[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < TPB / 64; ++w)
+            tot += wcnt[w];
+        base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)fill, (unsigned long long)tot)
+                       : 0;
+    }
+    __syncthreads();
+    if (wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3] > 0)
+        scatter_range(t, dt, T, b, e, base, act);
+}
+
 __global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed jm, JRecPair32 jp, JRecF64 jd,
                                                            int prec, int64_t n,
                                                            const int32_t *cluster_of,
@@ -436,14 +484,129 @@ __global__ __launch_bounds__(TPB) void scatter_pack_kernel(State st, JRecMixed j
                                                            const int32_t *chunk_cluster,
                                                            const double *tblock,
                                                            const int64_t *chunk_pos,
-                                                           int32_t *act, int64_t n_chunks)
+                                                           int32_t *act, int64_t n_chunks,
+                                                           int64_t *fill)
 {
-    if ((int64_t)blockIdx.x < n_chunks)
+    if ((int64_t)blockIdx.x < n_chunks && fill) {
+        const double T = tblock[0];
+        if (T < DBL_MAX)
+            scatter_chunk_fill(st.t, st.dt, T, chunk_begin[blockIdx.x],
+                               chunk_begin[blockIdx.x + 1], act, fill);
+    } else if ((int64_t)blockIdx.x < n_chunks)
         scatter_chunk(st.t, st.dt, chunk_begin, chunk_cluster, tblock, chunk_pos, act,
                       blockIdx.x);
     else
         pack_one(st, jm, jp, jd, prec, n, tblock, cluster_of, 0,
                  ((int64_t)blockIdx.x - n_chunks) * TPB + threadIdx.x);
+}
+
+// ------------------------------------------ schedule from per-level counts
+// For one system whose steps are powers of two dt_max 2^-k and whose
+// particles each sit at a multiple of their step, below the next one
+// (t_i <= T_last < t_i + dt_i, T_last the time of the last block), the next
+// block time is the earliest next multiple of an occupied level's step after
+// T_last, and the particles due then are exactly those of the levels whose
+// step divides it; no sweep over the particles is needed.  The counts are
+// built once per nbody_step call (and checked: any particle that breaks the
+// conditions sets lvl[LVL_BAD], and the sweep is used instead) and kept up to
+// date by the corrector.
+__global__ __launch_bounds__(TPB) void levels_build_kernel(const double *t, const double *dt,
+                                                           int64_t n, int e0, int kmax,
+                                                           int64_t *lvl)
+{
+    __shared__ int cnt[LVL_N];
+    if (threadIdx.x < LVL_N)
+        cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    uint64_t tb = 0;
+    if (i < n) {
+        const double ti = t[i], di = dt[i];
+        const uint64_t bits = (uint64_t)__double_as_longlong(di);
+        const int k = dt_level(di, e0);
+        // a power of two (zero mantissa, normal), on a level of [0, kmax],
+        // a time that is a non-negative multiple of the step
+        const bool ok = (bits & 0x000FFFFFFFFFFFFFull) == 0 && ((bits >> 52) & 0x7FF) != 0 &&
+                        (bits >> 63) == 0 && k >= 0 && k <= kmax && k < LVL_N && ti >= 0.0 &&
+                        floor(ti / di) * di == ti;
+        if (ok)
+            atomicAdd(&cnt[k], 1);
+        else
+            atomicOr((unsigned long long *)&lvl[LVL_BAD], 1ull);
+        tb = ti >= 0.0 ? (uint64_t)__double_as_longlong(ti) : 0;
+    }
+    const uint64_t tm = wave_max_u64(tb);
+    if ((threadIdx.x & 63) == 0)
+        atomicMax((unsigned long long *)&lvl[LVL_TPREV], (unsigned long long)tm);
+    __syncthreads();
+    if (threadIdx.x < LVL_N && cnt[threadIdx.x] != 0)
+        atomicAdd((unsigned long long *)&lvl[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+// second pass: every particle's next time lies beyond the last block
+__global__ __launch_bounds__(TPB) void levels_check_kernel(const double *t, const double *dt,
+                                                           int64_t n, int64_t *lvl)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double T = __longlong_as_double((long long)lvl[LVL_TPREV]);
+    if (!(t[i] + dt[i] > T))
+        atomicOr((unsigned long long *)&lvl[LVL_BAD], 1ull);
+}
+
+// One wave: the next block from the counts (the totals as sched_scan writes
+// them, into info and the mapped host words with the sequence number), the
+// time of the last block moved to it, and the active list's fill position
+// cleared.  A fill position that does not match the N_act announced by the
+// previous schedule (the compaction found other particles due than the counts
+// said) sets ERR_LEVELS.
+__global__ __launch_bounds__(64) void levels_sched_kernel(int64_t *lvl, int64_t n, int e0,
+                                                          double t_target, int64_t *seg,
+                                                          double *tblock, int64_t *info,
+                                                          int64_t *hist, uint32_t *err,
+                                                          int64_t *info_host, int64_t seq)
+{
+    const int k = threadIdx.x;
+    const int64_t c = lvl[k];
+    const double Tl = __longlong_as_double((long long)lvl[LVL_TPREV]);
+    const double step = ldexp(1.0, e0 - k);
+    const double next = c > 0 ? (floor(Tl / step) + 1.0) * step : INFINITY;
+    double T = next;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const double o = __shfl_xor(T, m, 64);
+        T = o < T ? o : T;
+    }
+    const bool act = T <= t_target;
+    int64_t na = act && c > 0 && next == T ? c : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        na += __shfl_xor(na, m, 64);
+    if (k != 0)
+        return;
+    if (lvl[LVL_POS] != lvl[LVL_NACT])
+        atomicOr(err, ERR_LEVELS);
+    lvl[LVL_POS] = 0;
+    lvl[LVL_NACT] = na;
+    const double Tb = act ? T : INFINITY;
+    if (na > 0) {
+        lvl[LVL_TPREV] = __double_as_longlong(T);
+        int bb = 0;
+        while ((int64_t(1) << (bb + 1)) <= na)
+            ++bb;
+        atomicAdd((unsigned long long *)&hist[bb], 1ull);
+    }
+    seg[0] = 0;
+    seg[1] = na;
+    tblock[0] = na > 0 ? T : INFINITY;
+    const int64_t tot[6] = {na, (int64_t)__double_as_longlong(Tb), na * n, (int64_t)*err,
+                            na > 0 ? 1 : 0, n};
+    for (int q = 0; q < 6; ++q) {
+        info[q] = tot[q];
+        info_host[q] = tot[q];
+    }
+    __hip_atomic_store(&info_host[6], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // i-block tables of a force launch over clusters: cluster c gets
@@ -633,27 +796,68 @@ __device__ __forceinline__ void correct_one(State st, int64_t n, int64_t i, cons
     correct_loaded(st, n, i, load_old(st, n, i), a1, j1, s1, t_target, eta, dt_min, dt_max, err);
 }
 
+// a workgroup's changes of the per-level counts (old step -> new step of the
+// particles it corrected), gathered in LDS and added to lvl[] once per level
+struct LevelDelta {
+    int *d;
+    __device__ void init()
+    {
+        __shared__ int sd[LVL_N];
+        d = sd;
+        if (threadIdx.x < LVL_N)
+            d[threadIdx.x] = 0;
+    }
+    __device__ void move(double dt_old, double dt_new, int e0)
+    {
+        const int a = dt_level(dt_old, e0), b = dt_level(dt_new, e0);
+        if (a != b && a >= 0 && a < LVL_N && b >= 0 && b < LVL_N) {
+            atomicAdd(&d[a], -1);
+            atomicAdd(&d[b], 1);
+        }
+    }
+    __device__ void flush(int64_t *lvl)
+    {
+        if (threadIdx.x < LVL_N && d[threadIdx.x] != 0)
+            atomicAdd((unsigned long long *)&lvl[threadIdx.x],
+                      (unsigned long long)(int64_t)d[threadIdx.x]);
+    }
+};
+
+// lvl: per-level counts to keep up to date (nullptr: none), e0 the exponent
+// of dt_max
 __global__ __launch_bounds__(TPB) void correct_kernel(
     State st, int64_t n, int64_t n_act, const int32_t *idx, double t_target,
     const double *fa, const double *fj, const double *fs, int64_t sk, int64_t sd,
-    double eta, double dt_min, double dt_max, uint32_t *err)
+    double eta, double dt_min, double dt_max, uint32_t *err, int64_t *lvl, int e0)
 {
+    LevelDelta ld;
+    if (lvl) {
+        ld.init();
+        __syncthreads();
+    }
     const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (k >= n_act)
-        return;
-    const int32_t i = idx[k];
-    if (i < 0 || i >= n) {   // a caller's list out of range: report, touch nothing
-        atomicOr(err, ERR_BADIDX);
-        return;
-    }
-    double a1[3], j1[3], s1[3];
+    if (k < n_act) {
+        const int32_t i = idx[k];
+        if (i < 0 || i >= n) {   // a caller's list out of range: report, touch nothing
+            atomicOr(err, ERR_BADIDX);
+        } else {
+            double a1[3], j1[3], s1[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        a1[d] = fa[k * sk + d * sd];
-        j1[d] = fj[k * sk + d * sd];
-        s1[d] = fs[k * sk + d * sd];
+            for (int d = 0; d < 3; ++d) {
+                a1[d] = fa[k * sk + d * sd];
+                j1[d] = fj[k * sk + d * sd];
+                s1[d] = fs[k * sk + d * sd];
+            }
+            const OldState o = load_old(st, n, i);
+            correct_loaded(st, n, i, o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+            if (lvl)
+                ld.move(o.h, st.dt[i], e0);
+        }
     }
-    correct_one(st, n, i, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+    if (lvl) {
+        __syncthreads();
+        ld.flush(lvl);
+    }
 }
 
 // Split-source reduction and corrector of a block step in one kernel: a
@@ -688,20 +892,28 @@ __device__ __forceinline__ double sum_splits(const double *p, int64_t stride, in
 __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
     State st, int64_t n, int64_t n_act, const double *part, int32_t B, int nt, ForceWork w,
     const int32_t *cluster_of, double t_target, double eta, double dt_min, double dt_max,
-    uint32_t *err)
+    uint32_t *err, int64_t *lvl, int e0)
 {
     __shared__ double sum[9][RC_SLOTS];
+    LevelDelta ld;
+    if (lvl)
+        ld.init();
     const int q = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
     const int64_t k0 = (int64_t)blockIdx.x * RC_SLOTS;
     const int64_t k = k0 + kl;
+    // an index outside the system (an active list that does not match the
+    // schedule): reported, the slot is left alone
+    const int64_t i = k < n_act ? w.idx[k] : -1;
+    const bool in = i >= 0 && i < n;
+    if (k < n_act && !in && threadIdx.x < RC_SLOTS)
+        atomicOr(err, ERR_BADIDX);
     // the lanes that run the corrector load its old state first, so that
     // those loads overlap the partial sums
-    const bool corr = threadIdx.x < RC_SLOTS && k < n_act;
+    const bool corr = threadIdx.x < RC_SLOTS && in;
     OldState o{};
     if (corr)
-        o = load_old(st, n, w.idx[k]);
-    if (q < 9 && k < n_act) {
-        const int64_t i = w.idx[k];
+        o = load_old(st, n, i);
+    if (q < 9 && in) {
         const int c = cluster_of ? cluster_of[i] : 0;
         const int64_t bc = splits_used(w.off[c + 1] - w.off[c], B, nt);
         sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
@@ -711,7 +923,13 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
         const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
         const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
         const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
-        correct_loaded(st, n, w.idx[k], o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+        correct_loaded(st, n, i, o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+        if (lvl)
+            ld.move(o.h, st.dt[i], e0);
+    }
+    if (lvl) {
+        __syncthreads();
+        ld.flush(lvl);
     }
 }
 
@@ -1437,14 +1655,37 @@ hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStre
 }
 
 // compaction of the active list and predictor of a block step, one launch
-hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s)
+hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s, bool levels)
 {
     const unsigned nb = (unsigned)c.n_chunks + nblk(c.n);
     hipLaunchKernelGGL(scatter_pack_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.jm, c.jp, c.jd,
                        (int)c.cfg.precision, c.n, (const int32_t *)c.d_cluster_of,
                        (const int64_t *)c.d_chunk_begin, (const int32_t *)c.d_chunk_cluster,
                        (const double *)c.d_tblock, (const int64_t *)c.d_chunk_pos, c.act,
-                       c.n_chunks);
+                       c.n_chunks, levels ? c.d_lvl + LVL_POS : (int64_t *)nullptr);
+    return hipGetLastError();
+}
+
+// per-level counts of the stored state (see levels_build_kernel)
+hipError_t launch_levels_build(const Ctx &c, hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(c.d_lvl, 0, LVL_WORDS * sizeof(int64_t), s);
+    if (e != hipSuccess)
+        return e;
+    const int e0 = std::ilogb(c.cfg.dt_max), e1 = std::ilogb(c.cfg.dt_min);
+    hipLaunchKernelGGL(levels_build_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s,
+                       (const double *)c.st.t, (const double *)c.st.dt, c.n, e0, e0 - e1,
+                       c.d_lvl);
+    hipLaunchKernelGGL(levels_check_kernel, dim3(nblk(c.n)), dim3(TPB), 0, s,
+                       (const double *)c.st.t, (const double *)c.st.dt, c.n, c.d_lvl);
+    return hipGetLastError();
+}
+
+hipError_t launch_levels_sched(const Ctx &c, double t_target, int64_t seq, hipStream_t s)
+{
+    hipLaunchKernelGGL(levels_sched_kernel, dim3(1), dim3(64), 0, s, c.d_lvl, c.n,
+                       std::ilogb(c.cfg.dt_max), t_target, c.d_seg, c.d_tblock, c.d_info,
+                       c.d_info + 8, c.d_err, c.d_tot, seq);
     return hipGetLastError();
 }
 
@@ -1612,18 +1853,19 @@ hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipS
 
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx, double t_target,
                           const double *fa, const double *fj, const double *fs, int64_t sk,
-                          int64_t sd, hipStream_t s)
+                          int64_t sd, hipStream_t s, bool levels)
 {
     if (n_act <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(correct_kernel, dim3(nblk(n_act)), dim3(TPB), 0, s, c.st, c.n, n_act,
                        idx, t_target, fa, fj, fs, sk, sd, c.cfg.eta, c.cfg.dt_min,
-                       c.cfg.dt_max, c.d_err);
+                       c.cfg.dt_max, c.d_err, levels ? c.d_lvl : nullptr,
+                       std::ilogb(c.cfg.dt_max));
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, int nt,
-                                 int64_t n_act, double t_target, hipStream_t s)
+                                 int64_t n_act, double t_target, hipStream_t s, bool levels)
 {
     if (n_act <= 0)
         return hipSuccess;
@@ -1631,7 +1873,8 @@ hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, in
     hipLaunchKernelGGL(reduce_correct_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.n, n_act,
                        (const double *)c.part, (int32_t)split, nt, w,
                        (const int32_t *)c.d_cluster_of, t_target, c.cfg.eta, c.cfg.dt_min,
-                       c.cfg.dt_max, c.d_err);
+                       c.cfg.dt_max, c.d_err, levels ? c.d_lvl : nullptr,
+                       std::ilogb(c.cfg.dt_max));
     return hipGetLastError();
 }
 

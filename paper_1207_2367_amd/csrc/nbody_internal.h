@@ -115,7 +115,8 @@ hipError_t launch_force(Ctx &c, const ForceWork &w, const Launch &L,
                         const ForceOut &out, int64_t n_act_total, hipStream_t s,
                         bool reduce = true);
 hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, int nt,
-                                 int64_t n_act, double t_target, hipStream_t s);
+                                 int64_t n_act, double t_target, hipStream_t s,
+                                 bool levels = false);
 Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src_max);
 Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec);
 // start-up evaluation (FP64, a, da, d2a and crackle of every particle from
@@ -138,8 +139,16 @@ hipError_t launch_predict_out(const Ctx &c, double t, double *pos, double *vel,
 hipError_t launch_schedule(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
 hipError_t launch_sched_reset(const Ctx &c, hipStream_t s);
 hipError_t launch_sched_head(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
+// per-level counts of the stored state, the time of the last block and the
+// check that every step is a power of two within [dt_min, dt_max] and every
+// particle's time a multiple of its step below the next one (d_lvl[LVL_BAD])
+hipError_t launch_levels_build(const Ctx &c, hipStream_t s);
+// the schedule of the next block from the counts (as launch_sched_head)
+hipError_t launch_levels_sched(const Ctx &c, double t_target, int64_t seq, hipStream_t s);
 hipError_t launch_sched_scatter(const Ctx &c, hipStream_t s);
-hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s);
+// compaction of the active list and predictor; with levels, the active list
+// is filled through an atomic position (chunks in any order)
+hipError_t launch_scatter_pack(const Ctx &c, hipStream_t s, bool levels = false);
 hipError_t launch_step_loop(const Ctx &c, double t_target, int64_t a_max, int grid, int64_t seq,
                             hipStream_t s);
 // workgroups of the device-resident loop that can be resident at once for
@@ -153,7 +162,8 @@ hipError_t launch_blocks(const Ctx &c, int64_t ib, int64_t cap, hipStream_t s);
 hipError_t launch_segments(const Ctx &c, const int32_t *idx, int64_t n_act, hipStream_t s);
 hipError_t launch_correct(const Ctx &c, int64_t n_act, const int32_t *idx,
                           double t_target, const double *fa, const double *fj,
-                          const double *fs, int64_t sk, int64_t sd, hipStream_t s);
+                          const double *fs, int64_t sk, int64_t sd, hipStream_t s,
+                          bool levels = false);
 hipError_t launch_recap(const Ctx &c, double t_target, hipStream_t s);
 hipError_t launch_energy_sums(const Ctx &c, const double *phi, double *out5,
                               hipStream_t s);
@@ -170,8 +180,17 @@ hipError_t launch_init_dt(const Ctx &c, hipStream_t s);
 
 // Device error word bits (set with atomicOr by kernels).
 enum : uint32_t {
-    ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u, ERR_LOOP = 8u, ERR_STATE = 16u
+    ERR_DTMIN = 1u, ERR_NONFINITE = 2u, ERR_BADIDX = 4u, ERR_LOOP = 8u, ERR_STATE = 16u,
+    ERR_LEVELS = 32u
 };
+
+// Schedule from per-level counts (a single system, nbody_step): lvl[k] =
+// number of particles whose step is dt_max 2^-k (k < LVL_N), then the time
+// of the last block (as bits), a violation flag, the active list's fill
+// position and the N_act the schedule announced.
+constexpr int LVL_N = 64;
+enum : int { LVL_TPREV = LVL_N, LVL_BAD = LVL_N + 1, LVL_POS = LVL_N + 2, LVL_NACT = LVL_N + 3,
+             LVL_WORDS = LVL_N + 4 };
 
 // Device-resident block-step loop: why it stopped, and the largest grid.
 enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
@@ -241,6 +260,8 @@ struct Ctx {
     int64_t sched_seq = 0;               // sequence number of the last schedule launched
     int64_t loop_seq = 0;                // same for the device-resident loop (h_tot[15])
     int64_t loop_amax = -1;              // loop's largest N_act: -1 automatic, 0 off
+    int64_t *d_lvl = nullptr;            // [LVL_WORDS] per-level counts (see LVL_N)
+    int sched_mode = 0;                  // 0: per-level counts where valid, 1: sweep only
     int loop_grid = -1;                  // its workgroups (-1: not yet queried, 0: none)
     uint64_t *d_loop_min = nullptr;      // [2 LOOP_GMAX] per-workgroup minima (two banks)
     int32_t *d_loop_cnt = nullptr;       // [2 LOOP_GMAX] and counts

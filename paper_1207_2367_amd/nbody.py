@@ -61,7 +61,8 @@ EXPORTS = [
     "nbody_default_config", "nbody_workspace_bytes", "nbody_init", "nbody_free",
     "nbody_force", "nbody_predict", "nbody_schedule", "nbody_correct", "nbody_block_step",
     "nbody_step", "nbody_get_state", "nbody_set_state", "nbody_energy", "nbody_autotune",
-    "nbody_set_launch", "nbody_get_launch", "nbody_set_step_loop", "nbody_strerror",
+    "nbody_set_launch", "nbody_get_launch", "nbody_set_step_loop", "nbody_set_schedule",
+    "nbody_strerror",
     "nbody_last_error",
     "nbody_profile", "nbody_profile_force_log", "nbody_force_noalloc",
     "nbody_get_tuning", "nbody_set_tuning",
@@ -103,6 +104,7 @@ def load():
         "nbody_set_tuning": (C.c_int, [vp, P(Launch), i32]),
         "nbody_get_launch": (C.c_int, [vp, i64, P(Launch)]),
         "nbody_set_step_loop": (C.c_int, [vp, i64]),
+        "nbody_set_schedule": (C.c_int, [vp, C.c_int]),
         "nbody_profile": (C.c_int, [vp, C.c_int, P(ProfileTimes)]),
         "nbody_profile_force_log": (i64, [vp, i64, vp, vp, vp]),
         "nbody_strerror": (C.c_char_p, [C.c_int]),
@@ -364,6 +366,11 @@ class System:
         """Device-resident block steps of step(): automatic limit (< 0),
         off (0) or at most max_active active particles per block."""
         self._check(load().nbody_set_step_loop(self.ctx, int(max_active)))
+
+    def set_schedule(self, mode=0):
+        """How step() finds the next block: 0 from per-level counts where the
+        state allows it (the default), 1 by a sweep of all particles."""
+        self._check(load().nbody_set_schedule(self.ctx, int(mode)))
 
     def profile(self, enable):
         """Start (enable=True, clears) or stop event timing of the phases;

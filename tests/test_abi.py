@@ -92,6 +92,7 @@ def test_strerror(lib):
 def test_null_context_calls_are_rejected(lib):
     from paper_1207_2367_amd import nbody
     assert lib.nbody_set_step_loop(None, -1) == nbody.EINVAL
+    assert lib.nbody_set_schedule(None, 0) == nbody.EINVAL
     assert lib.nbody_set_launch(None, None) == nbody.EINVAL
     assert lib.nbody_step(None, 1.0, None) == nbody.EINVAL
     assert lib.nbody_autotune(None, 10.0) == nbody.EINVAL
