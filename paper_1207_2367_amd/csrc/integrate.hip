@@ -861,11 +861,12 @@ __global__ __launch_bounds__(TPB) void correct_kernel(
 }
 
 // Split-source reduction and corrector of a block step in one kernel: a
-// workgroup takes RC_SLOTS active slots; thread (q, slot) sums quantity q
+// workgroup takes S active slots; R threads per (q, slot) sum quantity q
 // (a, da, d2a components) over the splits that hold the slot's cluster, in
-// the fixed order b = 0 .. B_c - 1 with 16 loads in flight, into LDS; then
-// one thread per slot runs the corrector on the sums.  part is the
-// evaluation's [B][10][n_act] buffer (the potential slot is not used).
+// a fixed order with 16 loads in flight, into LDS; then one thread per slot
+// runs the corrector on the sums.  part is the evaluation's [B][10][n_act]
+// buffer (the potential slot is not used).  The loops' own corrector phases
+// take RC_SLOTS slots with one thread per sum.
 constexpr int RC_SLOTS = TPB / 9;
 
 // sum of bc split partials p[0], p[stride], ... in the order b = 0 .. bc-1,
@@ -889,43 +890,64 @@ __device__ __forceinline__ double sum_splits(const double *p, int64_t stride, in
     return r;
 }
 
+// R lanes per (quantity, slot): lane r sums the splits [r bc / R, (r + 1)
+// bc / R) in order, and the corrector adds the R sums in the order r = 0 ..
+// R-1 (R = 1: one lane sums all splits in order).  More lanes per sum cut
+// the chain of dependent loads when a small block has many splits.
+template <int R>
 __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
     State st, int64_t n, int64_t n_act, const double *part, int32_t B, int nt, ForceWork w,
     const int32_t *cluster_of, double t_target, double eta, double dt_min, double dt_max,
     uint32_t *err, int64_t *lvl, int e0)
 {
-    __shared__ double sum[9][RC_SLOTS];
+    constexpr int S = TPB / (9 * R);   // active slots per workgroup
+    __shared__ double ps[9][S][R];
     LevelDelta ld;
     if (lvl)
         ld.init();
-    const int q = threadIdx.x / RC_SLOTS, kl = threadIdx.x % RC_SLOTS;
-    const int64_t k0 = (int64_t)blockIdx.x * RC_SLOTS;
-    const int64_t k = k0 + kl;
-    // an index outside the system (an active list that does not match the
-    // schedule): reported, the slot is left alone
-    const int64_t i = k < n_act ? w.idx[k] : -1;
-    const bool in = i >= 0 && i < n;
-    if (k < n_act && !in && threadIdx.x < RC_SLOTS)
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * S;
+    // corrector lanes: t < S takes slot t.  An index outside the system (an
+    // active list that does not match the schedule) is reported and the slot
+    // left alone.
+    const int64_t kc = k0 + t;
+    const int64_t ic = t < S && kc < n_act ? w.idx[kc] : -1;
+    if (t < S && kc < n_act && !(ic >= 0 && ic < n))
         atomicOr(err, ERR_BADIDX);
+    const bool corr = ic >= 0 && ic < n;
+    // summing lanes: (quantity q, slot kl, part r)
+    const int qk = t / R, r = t % R, q = qk / S, kl = qk % S;
+    const int64_t ks = k0 + kl;
+    const int64_t is = q < 9 && ks < n_act ? w.idx[ks] : -1;
     // the lanes that run the corrector load its old state first, so that
     // those loads overlap the partial sums
-    const bool corr = threadIdx.x < RC_SLOTS && in;
     OldState o{};
     if (corr)
-        o = load_old(st, n, i);
-    if (q < 9 && in) {
-        const int c = cluster_of ? cluster_of[i] : 0;
+        o = load_old(st, n, ic);
+    if (is >= 0 && is < n) {
+        const int c = cluster_of ? cluster_of[is] : 0;
         const int64_t bc = splits_used(w.off[c + 1] - w.off[c], B, nt);
-        sum[q][kl] = sum_splits(part + (int64_t)q * n_act + k, 10 * n_act, bc);
+        const int64_t b0 = r * bc / R, b1 = (r + 1) * bc / R;
+        ps[q][kl][r] = sum_splits(part + (int64_t)q * n_act + ks + b0 * 10 * n_act, 10 * n_act,
+                                  b1 - b0);
     }
     __syncthreads();
     if (corr) {
-        const double a1[3] = {sum[0][kl], sum[1][kl], sum[2][kl]};
-        const double j1[3] = {sum[3][kl], sum[4][kl], sum[5][kl]};
-        const double s1[3] = {sum[6][kl], sum[7][kl], sum[8][kl]};
-        correct_loaded(st, n, i, o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
+        double f[9];
+#pragma unroll
+        for (int qq = 0; qq < 9; ++qq) {
+            double v = ps[qq][t][0];
+#pragma unroll
+            for (int rr = 1; rr < R; ++rr)
+                v += ps[qq][t][rr];
+            f[qq] = v;
+        }
+        const double a1[3] = {f[0], f[1], f[2]};
+        const double j1[3] = {f[3], f[4], f[5]};
+        const double s1[3] = {f[6], f[7], f[8]};
+        correct_loaded(st, n, ic, o, a1, j1, s1, t_target, eta, dt_min, dt_max, err);
         if (lvl)
-            ld.move(o.h, st.dt[i], e0);
+            ld.move(o.h, st.dt[ic], e0);
     }
     if (lvl) {
         __syncthreads();
@@ -1869,8 +1891,13 @@ hipError_t launch_reduce_correct(const Ctx &c, const ForceWork &w, int split, in
 {
     if (n_act <= 0)
         return hipSuccess;
-    const unsigned nb = (unsigned)((n_act + RC_SLOTS - 1) / RC_SLOTS);
-    hipLaunchKernelGGL(reduce_correct_kernel, dim3(nb), dim3(TPB), 0, s, c.st, c.n, n_act,
+    // lanes per sum by the number of splits (chains of at most ~32 loads)
+    const int R = split <= 32 ? 1 : (split <= 128 ? 4 : 8);
+    const int S = TPB / (9 * R);
+    const unsigned nb = (unsigned)((n_act + S - 1) / S);
+    auto k = R == 1 ? reduce_correct_kernel<1> : (R == 4 ? reduce_correct_kernel<4>
+                                                           : reduce_correct_kernel<8>);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(TPB), 0, s, c.st, c.n, n_act,
                        (const double *)c.part, (int32_t)split, nt, w,
                        (const int32_t *)c.d_cluster_of, t_target, c.cfg.eta, c.cfg.dt_min,
                        c.cfg.dt_max, c.d_err, levels ? c.d_lvl : nullptr,

@@ -475,15 +475,21 @@ def etascan(n=None, precs="mixed,fp64", etas=(0.2, 0.3, 0.45, 0.6, 0.8, 1.0), t_
 
 def blocks32k(n=32768, t_end=1.0):
     """Where the time of a small-block integration goes: a 32,768-body
-    Plummer sphere (seed 7000 + n % 997, eta 0.45) to t = 1 with the phase
-    profile; per block step: wall time, GPU time by phase, evaluation
-    efficiency by N_act."""
+    Plummer sphere (seed 7000 + n % 997, eta 0.45) to t = 1 (schedule from
+    per-level counts, then from the sweep), then with the phase profile; per
+    block step: wall time, GPU time by phase, evaluation efficiency by
+    N_act."""
     import ics
     from paper_1207_2367_amd import PREC_MIXED, System
     n = int(n)
     m, x, v = ics.plummer(n, 7000 + n % 997)
     s = System(m, x, v, 1e-4, precision=PREC_MIXED)
     st0, wall0, _ = _run(s, float(t_end), profile=False, pieces=4)
+    # the same with the schedule from a sweep of every particle per block
+    # step instead of the per-level counts
+    s = System(m, x, v, 1e-4, precision=PREC_MIXED)
+    s.set_schedule(1)
+    st1, wall1, _ = _run(s, float(t_end), profile=False, pieces=4)
     # the same run again with the event timing of every phase (which adds
     # host work of its own)
     s = System(m, x, v, 1e-4, precision=PREC_MIXED)
@@ -496,6 +502,8 @@ def blocks32k(n=32768, t_end=1.0):
     s.autotune(50.0)
     st2, wall2, _ = _run(s, float(t_end), profile=False, pieces=4)
     return {"config": "blocks32k", "n": n, "block_steps": steps, "wall_s": wall0,
+            "wall_s_sweep_schedule": wall1, "block_steps_sweep_schedule": st1["block_steps"],
+            "us_per_block_step_sweep_schedule": wall1 / st1["block_steps"] * 1e6,
             "wall_s_autotuned": wall2, "block_steps_autotuned": st2["block_steps"],
             "wall_s_profiled": wall, "interactions": st["interactions"],
             "us_per_block_step": wall0 / st0["block_steps"] * 1e6,

@@ -193,6 +193,33 @@ def test_block_steps_match_oracle(prec):
             assert np.abs(g["x"] - it.x).max() < 1e-9
 
 
+@pytest.mark.parametrize("split", [64, 256])
+def test_block_steps_many_splits_match_oracle(split):
+    """The split sums of the corrector with several lanes per sum (4 lanes
+    from 33 splits on, 8 from 129): a pinned launch shape with 64 or 256
+    source splits (only the splits that hold sources count, so some lanes
+    sum none) keeps the FP64 block steps of the 1024-body sphere equal to
+    the oracle's, with states equal to roundoff."""
+    n = 1024
+    m, x, v = ics.plummer(n, 1001)
+    it = oracle.Integrator(m, x, v, EPS)
+    assert it.init(1.0) == 0
+    s = _system(m, x, v, 1)
+    s.set_state(**{k: getattr(it, k) for k in ("x", "v", "a", "jk", "sn", "cr", "t", "dt")})
+    s.set_launch(lanes_per_i=64, waves=4, split=split)
+    log_case(test="block_steps_many_splits", split=split)
+    for step in range(40):
+        err, na, tb = it.block_step(1.0)
+        gna, gtb = s.block_step(1.0)
+        assert err == 0
+        assert (gna, gtb) == (na, tb), step
+    g = {k: cpu(q) for k, q in s.get_state().items()}
+    dx = np.abs(g["x"] - it.x).max()
+    print(f"split {split}: max |dx| {dx:.2e}")
+    assert np.array_equal(g["t"], it.t) and np.array_equal(g["dt"], it.dt)
+    assert dx < 1e-13 and np.abs(g["v"] - it.v).max() < 1e-12
+
+
 def test_plummer_1024_to_t1_energy():
     """The 1024-body Plummer sphere, eps = 1e-4, eta = 0.45, dt_max = 1/16,
     to t = 1: oracle, GPU FP64 and GPU mixed.  Same block structure as the
