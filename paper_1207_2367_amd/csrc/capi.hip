@@ -253,7 +253,7 @@ int64_t nb::ws_layout(int64_t n, int32_t nc, int32_t prec, Ctx *c, char *base)
     int32_t *ens_i32 = nc > 1 ? (int32_t *)take((4 * LOOP_GMAX + 1 + nc) * 4) : nullptr;
     int64_t *ens_i64 = nc > 1 ? (int64_t *)take(4 * LOOP_GMAX * 8) : nullptr;
     unsigned long long *ens_res = nc > 1 ? (unsigned long long *)take(4 * 8) : nullptr;
-    uint32_t *loop_bar = (uint32_t *)take(LOOP_BAR_WORDS * 4);
+    uint32_t *loop_bar = (uint32_t *)take(2 * LOOP_BAR_WORDS * 4);
     uint32_t *err = (uint32_t *)take(4);
     const int64_t red_cap = 5 * (n / 256 + 2) + 16;
     double *red = (double *)take(red_cap * d);
@@ -667,7 +667,8 @@ int run_ensemble(Ctx &c, double t_target, nbody_step_stats *stats, bool *done)
     }
     if (c.ens_grid <= 0)
         return NBODY_OK;
-    HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 32 * c.ens_grid * sizeof(uint32_t), c.stream));
+    // barrier lines of the workgroups, then the groups' unit counters
+    HIPCHK(c, hipMemsetAsync(c.d_loop_bar, 0, 2 * LOOP_BAR_WORDS * sizeof(uint32_t), c.stream));
     HIPCHK(c, hipMemsetAsync(c.d_ens_res, 0, 4 * 8, c.stream));
     if (launch_ensemble_loop(c, t_target, c.ens_grid, c.ens, c.d_ens_res, c.stream) !=
         hipSuccess) {

@@ -99,22 +99,76 @@ __device__ __forceinline__ void pack_one(const State &st, const JRecMixed &jm,
     pack_h(st, jm, jp, jd, prec, n, i, h);
 }
 
+// the stored state of particle i that its prediction reads
+struct PredIn {
+    double x[3], v[3], a[3], j[3], s[3], c[3], m, t;
+};
+
+__device__ __forceinline__ PredIn load_pred(const State &st, int64_t n, int64_t i)
+{
+    PredIn q;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = (int64_t)d * n + i;
+        q.x[d] = st.pos[e];
+        q.v[d] = st.vel[e];
+        q.a[d] = st.acc[e];
+        q.j[d] = st.jrk[e];
+        q.s[d] = st.snp[e];
+        q.c[d] = st.crk[e];
+    }
+    q.m = st.mass[i];
+    q.t = st.t[i];
+    return q;
+}
+
+__device__ __forceinline__ void store_pred(const PredIn &q, const JRecMixed &jm,
+                                           const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                           int64_t i, double h);
+
 // the records of particle i advanced by h from its own time
 __device__ __forceinline__ void pack_h(const State &st, const JRecMixed &jm,
                                        const JRecPair32 &jp, const JRecF64 &jd, int prec,
                                        int64_t n, int64_t i, double h)
 {
+    store_pred(load_pred(st, n, i), jm, jp, jd, prec, i, h);
+}
+
+// the records of the particles [r0, r1) of one workgroup advanced to T, two
+// particles per lane and pass with all loads of both issued before either
+// particle's stores (the stores could alias the loads as far as the
+// compiler knows, so it would not overlap two passes by itself)
+__device__ __forceinline__ void pack_range(const State &st, const JRecMixed &jm,
+                                           const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                           int64_t n, int64_t r0, int64_t r1, double T)
+{
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 2 * TPB) {
+        const int64_t i2 = i + TPB;
+        const bool two = i2 < r1;
+        const PredIn a = load_pred(st, n, i);
+        PredIn b{};
+        if (two)
+            b = load_pred(st, n, i2);
+        store_pred(a, jm, jp, jd, prec, i, T - a.t);
+        if (two)
+            store_pred(b, jm, jp, jd, prec, i2, T - b.t);
+    }
+}
+
+__device__ __forceinline__ void store_pred(const PredIn &q, const JRecMixed &jm,
+                                           const JRecPair32 &jp, const JRecF64 &jd, int prec,
+                                           int64_t i, double h)
+{
     double xp[3], vp[3], ap[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int64_t e = (int64_t)d * n + i;
-        const double x = st.pos[e], v = st.vel[e], a = st.acc[e];
-        const double j = st.jrk[e], s = st.snp[e], c = st.crk[e];
+        const double x = q.x[d], v = q.v[d], a = q.a[d];
+        const double j = q.j[d], s = q.s[d], c = q.c[d];
         xp[d] = x + h * (v + h * (a * 0.5 + h * (j * (1.0 / 6) + h * (s * (1.0 / 24) + h * (c * (1.0 / 120))))));
         vp[d] = v + h * (a + h * (j * 0.5 + h * (s * (1.0 / 6) + h * (c * (1.0 / 24)))));
         ap[d] = a + h * (j + h * (s * 0.5 + h * (c * (1.0 / 6))));
     }
-    const double m = st.mass[i];
+    const double m = q.m;
     if (prec == NBODY_PREC_MIXED) {
         jm.x[i] = xp[0]; jm.y[i] = xp[1]; jm.z[i] = xp[2];
         jm.vx[i] = vp[0]; jm.vy[i] = vp[1]; jm.vz[i] = vp[2];
@@ -1173,8 +1227,7 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
         const int64_t mine = wmin[blockIdx.x] == T_bits ? (int64_t)wcnt[blockIdx.x] : 0;
         if (mine > 0)
             scatter_range(st.t, st.dt, T, r0, r1, first, act);
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += TPB)
-            pack_h(st, jm, jp, jd, prec, n, i, T - st.t[i]);
+        pack_range(st, jm, jp, jd, prec, n, r0, r1, T);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             seg[0] = 0;
             seg[1] = n_act;
@@ -1265,15 +1318,41 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
 // group).  Per-workgroup minima and counts are kept in two
 // banks by cluster parity: a workgroup that has finished a cluster may start
 // the next while a slower one still reads the last decision's values.
+// A group's evaluation units (i-block u % n_ib against split u / n_ib).  A
+// workgroup alone takes them in order; in a group of several, each
+// workgroup takes the next unit from the group's counter (*ctr, one atomic
+// add per unit) until none is left, so that a workgroup slowed by its
+// neighbours on the compute unit does not hold the others up.  The counter
+// is never reset: each pass advances it by the units plus one failed take
+// per workgroup, which every workgroup of the group adds to *base alike.
+// Which workgroup evaluates a unit does not change its partial sums.
 template <int PREC, bool EPS0, int LPI>
 __device__ __forceinline__ void ens_units(const typename Smem<PREC>::R &J, const ForceWork &w,
                                           double *part, int64_t n_act, double eps2, int64_t n_ib,
-                                          int64_t B, int r, int W)
+                                          int64_t B, int r, int W, uint32_t *ctr,
+                                          uint32_t &base)
 {
     const ForceOut none{};
-    for (int64_t u = r; u < n_ib * B; u += W)
+    const int64_t units = n_ib * B;
+    if (W == 1) {
+        for (int64_t u = 0; u < units; ++u)
+            force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
+                                                          (int)(u / n_ib));
+        return;
+    }
+    __shared__ uint32_t take;
+    for (;;) {
+        if (threadIdx.x == 0)
+            take = atomicAdd(ctr, 1u) - base;
+        __syncthreads();
+        const int64_t u = take;
+        __syncthreads();
+        if (u >= units)
+            break;
         force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
                                                       (int)(u / n_ib));
+    }
+    base += (uint32_t)(units + W);
 }
 
 // res (device): [0] sum of N_act, [1] sum of N_act * N_c, [2] largest number
@@ -1295,6 +1374,8 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
     double *gpart = part + plan.part_off[g] * 10;
     const int64_t cap = plan.part_cap[g];
     uint32_t epoch = 0;
+    // the group's unit counter: its own 128-byte line after the barrier lines
+    uint32_t *uctr = bar + LOOP_BAR_WORDS + LOOP_FLAG * g, ubase = 0;
     int64_t act_sum = 0, pairs = 0, steps_max = 0;
     bool failed = false;
     for (int q = plan.cl_off[g]; q < plan.cl_off[g + 1] && !failed; ++q) {
@@ -1344,6 +1425,8 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
             const int64_t mine = wm[blockIdx.x] == T_bits ? (int64_t)wc[blockIdx.x] : 0;
             if (mine > 0)
                 scatter_range(st.t, st.dt, T, r0, r1, first, act_c);
+            // one particle per lane and pass: the kernel is held to 128
+            // registers, and two in flight would spill
             for (int64_t i = r0 + threadIdx.x; i < r1; i += TPB)
                 pack_h(st, jm, jp, jd, prec, n, i, T - st.t[i]);
             if (r == 0 && threadIdx.x == 0) {
@@ -1362,14 +1445,15 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
                 break;
             }
             // (3) evaluation units of the group: i-blocks against source
-            // splits.  One workgroup takes the block in as few units as its
-            // lanes allow; a group of several wants about four units per
-            // workgroup, so that units of unequal length still balance:
-            // lanes per particle (1, 8 or 32) for that many lanes, then
-            // source splits for that many units.
+            // splits.  Lanes per particle: 1 when the active particles give
+            // every lane of the group one, else 8 when they fill one
+            // workgroup's lanes, else 32 (fewer lanes per particle mean
+            // more pairs per lane and LDS tile, so the tile loads and lane
+            // reductions cost less per pair).  Then source splits until a
+            // group of several has about four units per workgroup (a
+            // workgroup alone takes the block in as few units as possible).
             const int64_t units = W == 1 ? 1 : 4 * (int64_t)W;
-            const int64_t need = ((int64_t)TPB * units + n_act - 1) / n_act;
-            const int lpi = need <= 1 ? 1 : (need <= 8 ? 8 : 32);
+            const int lpi = n_act >= (int64_t)TPB * W ? 1 : (n_act * 8 >= TPB ? 8 : 32);
             const int64_t ib = (int64_t)LOOP_NW * (64 / lpi);
             const int64_t n_ib = (n_act + ib - 1) / ib;
             int64_t B = 1;
@@ -1384,11 +1468,14 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
             w.nc = 1;
             w.n_blocks = n_ib;
             if (lpi == 32)
-                ens_units<PREC, EPS0, 32>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+                ens_units<PREC, EPS0, 32>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                                          ubase);
             else if (lpi == 8)
-                ens_units<PREC, EPS0, 8>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+                ens_units<PREC, EPS0, 8>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                                         ubase);
             else
-                ens_units<PREC, EPS0, 1>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W);
+                ens_units<PREC, EPS0, 1>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                                         ubase);
             if (!group_sync(bar, f, W, err, epoch)) {
                 failed = true;
                 break;

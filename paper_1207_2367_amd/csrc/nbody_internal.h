@@ -272,7 +272,8 @@ struct Ctx {
     int64_t *d_ens_i64 = nullptr;        // part_off, part_cap, seg
     int ens_grid = -1;
     unsigned long long *d_ens_res = nullptr;   // [4]
-    uint32_t *d_loop_bar = nullptr;      // [LOOP_BAR_WORDS] grid barrier words
+    uint32_t *d_loop_bar = nullptr;      // [2 LOOP_BAR_WORDS] barrier words, then the ensemble
+                                         // groups' unit counters (a line per group)
     int64_t *d_tot = nullptr;            // device address of h_tot
     double *h_red = nullptr;
     uint32_t *h_err = nullptr;
