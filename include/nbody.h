@@ -288,7 +288,7 @@ int nbody_set_tuning(nbody_ctx *ctx, const nbody_launch *table, int32_t count);
    through the host-sized path and the loop resumes after it.  Results
    equal the host-sized path's to the rounding of the split sums (a
    different launch shape).  max_active < 0 (the default): automatic, i.e.
-   on for systems of up to 8192 bodies with blocks of up to ~2^21 pairs
+   on for systems of up to 4096 bodies with blocks of up to ~2^21 pairs
    (at least 4 particles), off for larger systems, where the host-sized
    path is faster; 0: off; > 0: on with that limit (capped by the
    split-partials capacity).  If the runtime refuses the cooperative

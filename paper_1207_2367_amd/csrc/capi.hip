@@ -698,9 +698,9 @@ int run_ensemble(Ctx &c, double t_target, nbody_step_stats *stats, bool *done)
 // with the number of workgroups, and the loop's few workgroups evaluate a
 // large block at low occupancy, so the loop uses 64 workgroups, takes blocks
 // of up to ~2^21 pairs, and is switched on automatically for systems of up
-// to 8192 bodies only (there it cuts the time per block step by a quarter;
-// at 16k bodies it breaks even and beyond it is slower than the host-sized
-// path).
+// to 4096 bodies only (there it cuts the time per block step by 7-15 %
+// against the host-sized path with its schedule from per-level counts; at
+// 6144 bodies and beyond it is slower).
 // *reason: LOOP_DONE (every particle at the target), LOOP_BIG (the next
 // block is larger than the limit: the host path takes it) or 0 when the
 // loop is not used.

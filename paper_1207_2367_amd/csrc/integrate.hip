@@ -1021,14 +1021,14 @@ __global__ __launch_bounds__(TPB) void reduce_correct_kernel(
 //       when N_act exceeds a_max (the host path takes that block) or when
 //       the error word is set; otherwise each writes the ascending active
 //       list of its range and predicts its range's sources to T -> barrier;
-//   (3) the evaluation units (i-blocks of LOOP_IB active particles against
-//       one of B source splits) are dealt round-robin -> barrier;
+//   (3) the evaluation units (i-blocks of active particles against one of
+//       B source splits, shaped as in the ensemble loop) are taken from a
+//       shared counter -> barrier;
 //   (4) each workgroup sums the split partials of its own range's active
 //       particles in the order b = 0 .. B-1 and runs the corrector on them.
 // The next sweep (1) reads only the workgroup's own range, which only that
 // workgroup has changed in (4): a workgroup barrier is enough there.
-constexpr int LOOP_LPI = 64, LOOP_NW = 4;                 // evaluation shape
-constexpr int LOOP_IB = LOOP_NW * (64 / LOOP_LPI);        // active slots per unit
+constexpr int LOOP_NW = 4;                                // waves per workgroup
 constexpr int LOOP_NT = LOOP_NW * 64;                     // sources per tile
 constexpr int LOOP_BMAX = 64;                             // largest split
 constexpr uint32_t LOOP_SPINS = 1u << 21;                 // barrier wait bound (~2 s)
@@ -1165,6 +1165,44 @@ __device__ __forceinline__ const typename Smem<PREC>::R &loop_records(const JRec
         return jd;
 }
 
+// A group's evaluation units (i-block u % n_ib against split u / n_ib).  A
+// workgroup alone takes them in order (without a counter, workgroup r of W
+// takes every W-th from r); in a group of several, each
+// workgroup takes the next unit from the group's counter (*ctr, one atomic
+// add per unit) until none is left, so that a workgroup slowed by its
+// neighbours on the compute unit does not hold the others up.  The counter
+// is never reset: each pass advances it by the units plus one failed take
+// per workgroup, which every workgroup of the group adds to *base alike.
+// Which workgroup evaluates a unit does not change its partial sums.
+template <int PREC, bool EPS0, int LPI>
+__device__ __forceinline__ void group_units(const typename Smem<PREC>::R &J, const ForceWork &w,
+                                          double *part, int64_t n_act, double eps2, int64_t n_ib,
+                                          int64_t B, int r, int W, uint32_t *ctr,
+                                          uint32_t &base)
+{
+    const ForceOut none{};
+    const int64_t units = n_ib * B;
+    if (W == 1 || !ctr) {   // alone, or no counter: round-robin
+        for (int64_t u = r; u < units; u += W)
+            force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
+                                                          (int)(u / n_ib));
+        return;
+    }
+    __shared__ uint32_t take;
+    for (;;) {
+        if (threadIdx.x == 0)
+            take = atomicAdd(ctr, 1u) - base;
+        __syncthreads();
+        const int64_t u = take;
+        __syncthreads();
+        if (u >= units)
+            break;
+        force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
+                                                      (int)(u / n_ib));
+    }
+    base += (uint32_t)(units + W);
+}
+
 // res (mapped host memory): [0] block steps, [1] sum of N_act, [2] sum of
 // N_act * n, [3] reason (LOOP_DONE, LOOP_BIG, LOOP_ERR), [4] N_act of the
 // block it stopped at, then [7] = seq with system-scope release order.
@@ -1185,6 +1223,9 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
     int64_t steps = 0, act_sum = 0, pairs = 0, stop_n = 0;
     int reason = 0;
     uint32_t epoch = 0;
+    // unit counter (group_units): barrier line 2, or none for fewer than
+    // three workgroups (only lines 0 and 1 are cleared then)
+    uint32_t *uctr = G >= 3 ? bar + LOOP_FLAG * 2 : nullptr, ubase = 0;
 
     uint64_t v;
     int cnt;
@@ -1243,10 +1284,17 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
             reason = LOOP_ERR;
             break;
         }
-        // (3) evaluation units: i-block g against split b
-        const int64_t n_ib = (n_act + LOOP_IB - 1) / LOOP_IB;
+        // (3) evaluation units, shaped and taken as in the ensemble loop's
+        // groups (the loop's workgroups are one group): 1, 8 or 32 lanes
+        // per particle, then source splits for about four units per
+        // workgroup, each workgroup taking the next unit from the counter in
+        // the barrier line 2 (cleared with the others before the launch)
+        const int64_t units = 4 * (int64_t)G;
+        const int lpi = n_act >= (int64_t)TPB * G ? 1 : (n_act * 8 >= TPB ? 8 : 32);
+        const int64_t ib = (int64_t)LOOP_NW * (64 / lpi);
+        const int64_t n_ib = (n_act + ib - 1) / ib;
         int64_t B = 1;
-        while (B * 2 <= LOOP_BMAX && B * 2 * n_ib <= 2 * (int64_t)G && B * 2 * LOOP_NT <= n)
+        while (B * 2 <= LOOP_BMAX && B * n_ib < units && B * 2 * LOOP_NT <= n)
             B *= 2;
         ForceWork w{};
         w.idx = act;
@@ -1255,10 +1303,15 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
         w.split = (int32_t)B;
         w.nc = 1;
         w.n_blocks = n_ib;
-        const ForceOut none{};
-        for (int64_t u = blockIdx.x; u < n_ib * B; u += G)
-            force_block<PREC, LOOP_LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2,
-                                                                u % n_ib, (int)(u / n_ib));
+        if (lpi == 32)
+            group_units<PREC, EPS0, 32>(J, w, part, n_act, eps2, n_ib, B, (int)blockIdx.x, (int)G,
+                                        uctr, ubase);
+        else if (lpi == 8)
+            group_units<PREC, EPS0, 8>(J, w, part, n_act, eps2, n_ib, B, (int)blockIdx.x, (int)G,
+                                       uctr, ubase);
+        else
+            group_units<PREC, EPS0, 1>(J, w, part, n_act, eps2, n_ib, B, (int)blockIdx.x, (int)G,
+                                       uctr, ubase);
         if (!grid_sync(bar, G, err, epoch)) {
             reason = LOOP_ERR;
             break;
@@ -1318,43 +1371,6 @@ __global__ __launch_bounds__(TPB) void step_loop_kernel(
 // group).  Per-workgroup minima and counts are kept in two
 // banks by cluster parity: a workgroup that has finished a cluster may start
 // the next while a slower one still reads the last decision's values.
-// A group's evaluation units (i-block u % n_ib against split u / n_ib).  A
-// workgroup alone takes them in order; in a group of several, each
-// workgroup takes the next unit from the group's counter (*ctr, one atomic
-// add per unit) until none is left, so that a workgroup slowed by its
-// neighbours on the compute unit does not hold the others up.  The counter
-// is never reset: each pass advances it by the units plus one failed take
-// per workgroup, which every workgroup of the group adds to *base alike.
-// Which workgroup evaluates a unit does not change its partial sums.
-template <int PREC, bool EPS0, int LPI>
-__device__ __forceinline__ void ens_units(const typename Smem<PREC>::R &J, const ForceWork &w,
-                                          double *part, int64_t n_act, double eps2, int64_t n_ib,
-                                          int64_t B, int r, int W, uint32_t *ctr,
-                                          uint32_t &base)
-{
-    const ForceOut none{};
-    const int64_t units = n_ib * B;
-    if (W == 1) {
-        for (int64_t u = 0; u < units; ++u)
-            force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
-                                                          (int)(u / n_ib));
-        return;
-    }
-    __shared__ uint32_t take;
-    for (;;) {
-        if (threadIdx.x == 0)
-            take = atomicAdd(ctr, 1u) - base;
-        __syncthreads();
-        const int64_t u = take;
-        __syncthreads();
-        if (u >= units)
-            break;
-        force_block<PREC, LPI, LOOP_NW, EPS0, false>(J, w, none, part, n_act, eps2, u % n_ib,
-                                                      (int)(u / n_ib));
-    }
-    base += (uint32_t)(units + W);
-}
-
 // res (device): [0] sum of N_act, [1] sum of N_act * N_c, [2] largest number
 // of block steps of a cluster (the number of batched block steps of the
 // host-sized path)
@@ -1468,13 +1484,13 @@ __global__ __launch_bounds__(TPB, 4) void ensemble_loop_kernel(
             w.nc = 1;
             w.n_blocks = n_ib;
             if (lpi == 32)
-                ens_units<PREC, EPS0, 32>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                group_units<PREC, EPS0, 32>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
                                           ubase);
             else if (lpi == 8)
-                ens_units<PREC, EPS0, 8>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                group_units<PREC, EPS0, 8>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
                                          ubase);
             else
-                ens_units<PREC, EPS0, 1>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
+                group_units<PREC, EPS0, 1>(J, w, gpart, n_act, eps2, n_ib, B, r, (int)W, uctr,
                                          ubase);
             if (!group_sync(bar, f, W, err, epoch)) {
                 failed = true;

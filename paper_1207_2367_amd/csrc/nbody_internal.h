@@ -196,7 +196,7 @@ enum : int { LVL_TPREV = LVL_N, LVL_BAD = LVL_N + 1, LVL_POS = LVL_N + 2, LVL_NA
 enum : int { LOOP_DONE = 1, LOOP_BIG = 2, LOOP_ERR = 3 };
 constexpr int LOOP_GMAX = 1024;
 constexpr int LOOP_GRID = 64;            // workgroups the loop uses
-constexpr int64_t LOOP_AUTO_NMAX = 8192; // automatic mode: systems up to this size
+constexpr int64_t LOOP_AUTO_NMAX = 4096; // automatic mode: systems up to this size
 constexpr int64_t LOOP_BAR_WORDS = 32 * LOOP_GMAX;         // barrier lines (128 B each)
 // largest group of the ensemble loop (a barrier's cost grows with the
 // group's size: beyond 256 workgroups it outweighs the extra lanes)
