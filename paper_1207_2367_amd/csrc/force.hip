@@ -6,22 +6,26 @@
 // Design (CDNA4, wave64):
 //   - one workgroup = NW waves; each wave holds GI = 64 / LPI active
 //     particles, LPI lanes per particle; the i-particle lives in registers;
-//   - sources are staged through LDS in structure-of-arrays tiles of
-//     NT = 64 NW records, loaded coalesced by the whole workgroup; lane
-//     slot js of an i-particle takes tile entries js, js + LPI, ...; with
-//     LPI = 1 every LDS read is a broadcast;
+//   - sources are staged through LDS in tiles of NT = 64 NW records (one
+//     16-byte aligned record per source), loaded coalesced from the
+//     structure-of-arrays source arrays by the whole workgroup; lane slot js
+//     of an i-particle takes tile entries js, js + LPI, ...; with LPI = 1
+//     every LDS read is a broadcast;
 //   - the pair loop is pure vector ALU: no matrix cores, the work is not a
 //     dense contraction (every pair needs a reciprocal square root and
 //     nonlinear terms);
 //   - mixed precision: r_j - r_i, r^2 and 1/r (v_rsq_f32 seed + one FP64
-//     Newton step) in FP64, and with them the acceleration and potential
-//     terms, summed in FP64; the jerk and snap terms in FP32 from the
-//     rounded r_j - r_i, FP32 velocity and acceleration differences, summed
-//     over at most 64 pairs per lane in FP32 and folded into double-single
-//     (hi, lo) accumulators by an error-free two-sum.  The split follows
-//     where the method amplifies errors: the fifth-derivative estimate of
-//     the step criterion multiplies the acceleration's absolute error by
-//     ~720/h^5 but the jerk's and snap's by at most ~1/h^4 and ~1/h^3;
+//     Newton step) in FP64, and with them the acceleration, jerk (from FP64
+//     velocity differences) and potential terms, summed in FP64; the snap
+//     term in FP32 from the rounded r_j - r_i, jerk vector and coefficients
+//     and the FP32 acceleration differences, summed over at most 64 pairs
+//     per lane in FP32 and folded into double-single (hi, lo) accumulators
+//     by an error-free two-sum.  Per-term FP32 rounding in a sum with
+//     cancellation grows with the sum's condition number, so the quantities
+//     held to 1e-6 per particle (acceleration, jerk, potential) stay FP64;
+//     the snap is the least amplified: the fifth-derivative estimate of the
+//     step criterion multiplies the acceleration's absolute error by
+//     ~720/h^5 but the snap's by at most ~1/h^3;
 //   - the LPI lanes of a particle are combined by a xor butterfly of wave
 //     shuffles (bitwise identical on every lane, fixed order);
 //   - the FP64 passes take 1/r from the same FP32 seed, refined to FP64
@@ -65,6 +69,26 @@ __device__ __forceinline__ double pot_tile(const double *sx, const double *sy,
     return phi;
 }
 
+// Which (i-block, split) a workgroup of a launch takes.  The hardware deals
+// consecutive workgroups (x fastest) to the NXCD XCDs in turn, and each XCD
+// has an L2 of its own: taken as (blockIdx.x, blockIdx.y), the i-blocks that
+// run side by side on one XCD belong to several splits, and every XCD
+// fetches every split's source records from memory.  Renumbered so that XCD
+// k takes the k-th contiguous run of the pairs in x-fastest order, the
+// workgroups resident on one XCD walk the same split's tiles together and
+// share them in its L2.  A bijection of the grid for any size: the first
+// (total mod NXCD) XCDs get one pair more.
+__device__ __forceinline__ void xcd_order(int64_t &g, int &b)
+{
+    constexpr uint64_t NXCD = 8;
+    const uint64_t nx = gridDim.x, tot = nx * gridDim.y;
+    const uint64_t id = blockIdx.x + (uint64_t)blockIdx.y * nx;
+    const uint64_t x = id % NXCD, r = id / NXCD, q = tot / NXCD, rem = tot % NXCD;
+    const uint64_t l = x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+    g = (int64_t)(l % nx);
+    b = (int)(l / nx);
+}
+
 // PHI: also sum the potential (nbody_force, the start-up pass); a block
 // step's evaluation does not need it (the energy has its own pass).  IPT:
 // active particles per lane group.
@@ -73,8 +97,10 @@ __global__ __launch_bounds__(NW * 64) void force_kernel(
     typename Smem<PREC>::R J, ForceWork w, ForceOut out, double *part,
     int64_t n_act_total, double eps2)
 {
-    force_block<PREC, LPI, NW, EPS0, PHI, IPT>(J, w, out, part, n_act_total, eps2,
-                                               blockIdx.x, blockIdx.y);
+    int64_t g;
+    int b;
+    xcd_order(g, b);
+    force_block<PREC, LPI, NW, EPS0, PHI, IPT>(J, w, out, part, n_act_total, eps2, g, b);
 }
 
 // Potential energy of the stored state (paper Sect. 5.1): every unordered
