@@ -50,6 +50,7 @@ EPS = 1e-4
 N_BIG, NACT_BIG, SEED_BIG, SEED_SUB = 1 << 23, 65536, 5005, 5006
 N_MICRO, SEED_MICRO, SEED_MICRO_SUB = 65536, 2002, 2003
 MICRO_NACTS = (1, 64, 1024, 8192, 65536)
+MICRO_WARM, MICRO_REPS = 3, 15   # untimed and timed calls per size (median reported)
 DT_ACTIVE, DT_REST = 2.0 ** -10, 1.0 / 16
 # algorithmic flops per pair (FMA = 2, rsqrt = 4; the count of the method's
 # difference, distance, rsqrt, alpha/beta, A/J/S and accumulation terms)
@@ -168,7 +169,8 @@ class BigStep:
 
 def micro_sizes(precisions):
     """The 65,536-body force microbenchmark: for N_act = 1 ... 65,536 the
-    evaluation kernel's time (nbody_force after the autotuner) and the
+    evaluation's time (nbody_force after the autotuner; the median of
+    MICRO_REPS event-timed calls after MICRO_WARM untimed ones) and the
     per-particle errors of up to 512 active particles against the oracle."""
     import numpy as np
     import torch
@@ -180,27 +182,34 @@ def micro_sizes(precisions):
     m, x, v = ics.plummer(n, SEED_MICRO)
     a = ics.plummer_mean_acc(x)
     out = {}
+    # the oracle first: the GPU's clock drops while it idles, and the small
+    # sizes are timed right after a few warm-up calls
+    subsets = {}
     refs = {}
+    for na in MICRO_NACTS:
+        idx = ics.active_subset(n, na, SEED_MICRO_SUB)
+        pos = np.arange(na) if na <= 512 else np.sort(
+            np.random.default_rng(na).choice(na, 512, replace=False))
+        subsets[na] = (idx, pos)
+        refs[na] = oracle.force(m, x, v, a, EPS, idx[pos])
     for name, prec in precisions:
         s = System(m, x, v, EPS, precision=prec, skip_startup=True)
         s.set_state(a=a)
         s.autotune(150.0)
         res = {}
         for na in MICRO_NACTS:
-            idx = ics.active_subset(n, na, SEED_MICRO_SUB)
-            pos = np.arange(na) if na <= 512 else np.sort(
-                np.random.default_rng(na).choice(na, 512, replace=False))
-            if na not in refs:
-                refs[na] = oracle.force(m, x, v, a, EPS, idx[pos])
+            idx, pos = subsets[na]
             idx_dev = torch.as_tensor(idx, device="cuda").to(torch.int32)
             got = s.force(idx_dev)
+            for _ in range(MICRO_WARM):
+                s.force(idx_dev)
             s.profile(True)
-            for _ in range(3):
+            for _ in range(MICRO_REPS):
                 s.force(idx_dev)
             torch.cuda.synchronize()
             s.profile(False)
             lna, _, lms = s.force_log()
-            t = float(lms[lna == na].mean())
+            t = float(np.median(lms[lna == na]))
             lp = s.get_launch(na)
             res[str(na)] = {"kernel_ms": round(t, 5),
                             "G_interactions_per_s": round(na * n / (t * 1e-3) / 1e9, 3),

@@ -9,9 +9,12 @@
 // state with one particle per lane (coalesced), keep every per-particle
 // temporary in registers and write each output once.  Reductions run in a
 // fixed tree order, so two identical runs give identical bits.  The file
-// also holds the device-resident loop that runs whole block steps of a
-// small system inside one cooperative launch (step_loop_kernel), with the
-// evaluation body of force_body.h.
+// also holds the schedule from per-level counts of the power-of-two steps
+// (levels_*), the device-resident loop that runs whole block steps of a
+// small system inside one cooperative launch (step_loop_kernel) and the
+// ensemble loop that runs every block step of every cluster of a batched
+// context in one launch (ensemble_loop_kernel), both with the evaluation
+// body of force_body.h.
 #include <cfloat>
 #include <cmath>
 
