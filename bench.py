@@ -341,15 +341,16 @@ def summarize_profile(d):
             out.append(f"{len(v):5d} {sum(v):9.3f} {statistics.mean(v):9.5f} {statistics.median(v):9.5f} "
                        f"{min(v):9.5f} {max(v):9.5f} {100 * sum(v) / tot:6.2f}%  {key[1]} x {key[2]} "
                        f"({key[3]})  {short}")
-        # the dominant kernel of the bench: the shape of the last mixed-mode
-        # evaluation longer than 1 ms; its dispatches in launch order
+        # the dominant kernel of the bench: the mixed-mode evaluation shape
+        # with the largest total time; its dispatches in launch order
         mixed = sorted((r for r in rows if "force_kernel<0," in r["Kernel_Name"]),
                        key=lambda r: int(r["Start_Timestamp"]))
-        mixed_long = [r for r in mixed
-                      if int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) > 1_000_000]
-        if mixed_long:
-            r = mixed_long[-1]
+        by_shape = {}
+        for r in mixed:
             shape = (r["Kernel_Name"], r["Grid_Size_X"], r["Grid_Size_Y"])
+            by_shape[shape] = by_shape.get(shape, 0) + int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        if by_shape:
+            shape = max(by_shape, key=by_shape.get)
             seq = [r for r in mixed if (r["Kernel_Name"], r["Grid_Size_X"], r["Grid_Size_Y"]) == shape]
             seq.sort(key=lambda r: int(r["Start_Timestamp"]))
             durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in seq]

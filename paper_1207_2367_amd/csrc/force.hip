@@ -318,8 +318,15 @@ Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
 // sets of 2^15 and more in the modes with FP64 pair arithmetic (it halves
 // the LDS reads per pair: 1-3 % faster there, measured; the FP32-pair mode
 // is faster with one); then split the sources while every split keeps two
-// tiles, the grid stays within 2^19 lanes and the partials (split x N_act
-// slots) fit part_cap.
+// tiles, the partials (split x N_act slots) fit part_cap, and either the
+// grid stays within 2^19 lanes or every split still holds 2^17 sources or
+// more.  The second clause is for large source sets: there a split's work
+// dwarfs its partials' traffic, and a grid of many more workgroups than the
+// chip holds at once (3 per CU at the mixed kernel's register use) leaves
+// a shorter partly empty last round.  Measured at 65,536 active x 8,388,608
+// sources: split 16 / 32 / 64 / 128 / 256 -> 946 / 935 / 930 / 927 / 925 ms,
+// but 3.4 / 4.5 / 6.8 / 11.2 / 20.2 GB fetched (shorter walks, started at
+// staggered times, share the L2 less); 2^17 stops at 64.
 Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
 {
     Launch L;
@@ -330,10 +337,14 @@ Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
         L.lpi <<= 1;
     L.ipt = prec != NBODY_PREC_FP32PAIR && L.lpi <= 4 && n_act * L.lpi >= (int64_t(1) << 15) ? 2 : 1;
     const int64_t nt = 64 * L.waves;
-    const int64_t max_lanes = int64_t(1) << 19;
-    while (n_act * L.lpi / L.ipt * L.split * 2 <= max_lanes &&
-           n_src / ((int64_t)L.split * 2) >= 2 * nt && (int64_t)L.split * 2 * n_act <= part_cap)
+    const int64_t max_lanes = int64_t(1) << 19, long_split = int64_t(1) << 17;
+    for (;;) {
+        const int64_t b2 = (int64_t)L.split * 2, per_split = n_src / b2;
+        if (per_split < 2 * nt || b2 * n_act > part_cap ||
+            (n_act * L.lpi / L.ipt * b2 > max_lanes && per_split < long_split))
+            break;
         L.split <<= 1;
+    }
     return L;
 }
 

@@ -24,7 +24,10 @@ def test_kernel_trace_summary(tmp_path, capsys):
     rows = [[mixed, 65536, 16, 256, 0, 2_000_000],          # 2 ms
             ["nb::sched_min(x)", 4096, 1, 256, 3_000_000, 3_005_000],
             [mixed, 65536, 16, 256, 4_000_000, 10_000_000],  # 6 ms
-            [mixed, 65536, 16, 256, 11_000_000, 15_000_000]]  # 4 ms
+            [mixed, 65536, 16, 256, 11_000_000, 15_000_000],  # 4 ms
+            # a later, shorter mixed evaluation of another shape (a microbenchmark
+            # size): the dominant shape is the one with the largest total time
+            [mixed, 32768, 1, 256, 16_000_000, 19_000_000]]  # 3 ms
     _write(d / "kt_kernel_trace.csv", hdr, rows)
     _write(d / "kt_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs"],
            [[mixed, 3, 12_000_000, 4_000_000], ["nb::sched_min(x)", 1, 5000, 5000]])
@@ -33,7 +36,7 @@ def test_kernel_trace_summary(tmp_path, capsys):
     line = [l for l in out.splitlines() if "force_kernel<0, 1, 4" in l and "x 16" in l][0]
     calls, total, avg, med = line.split()[:4]
     assert (int(calls), float(total), float(avg), float(med)) == (3, 12.0, 4.0, 4.0)
-    assert "3 dispatches in launch order (ms): 2.0000 6.0000 4.0000" in out
+    assert "grid 65536 x 16: 3 dispatches in launch order (ms): 2.0000 6.0000 4.0000" in out
     assert "--stats" in out and "12.000" in out
 
 
