@@ -584,7 +584,10 @@ def main():
                                           "kernel_tflops")}
                      | {"frac_fp64_peak": round(f64["kernel_tflops"] / PEAK_FP64, 4)},
         "fp32pair_path": {k: other["fp32pair"][k] for k in ("value", "unit", "ms_per_step",
-                                                              "kernel_ms", "kernel_tflops")},
+                                                              "kernel_ms", "kernel_tflops")}
+                         | {"frac_fp32_peak": round(other["fp32pair"]["kernel_tflops"] / PEAK_FP32, 4),
+                            "note": "every pair term in FP32: misses 1e-6 per particle for the "
+                                    "jerk of some particles (errors_vs_oracle.fp32pair)"},
         "speedup_mixed_vs_fp64": round(value / f64["value"], 3),
         "kernel_speedup_mixed_vs_fp64": round(f64["kernel_ms"] / avg_ms, 3),
         "kernel_speedup_fp32pair_vs_fp64": round(f64["kernel_ms"] / other["fp32pair"]["kernel_ms"], 3),
