@@ -340,7 +340,7 @@ Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
     const int64_t max_lanes = int64_t(1) << 19, long_split = int64_t(1) << 17;
     for (;;) {
         const int64_t b2 = (int64_t)L.split * 2, per_split = n_src / b2;
-        if (per_split < 2 * nt || b2 * n_act > part_cap ||
+        if (per_split < 2 * nt || b2 * n_act > part_cap || b2 > 65535 ||   // grid y limit
             (n_act * L.lpi / L.ipt * b2 > max_lanes && per_split < long_split))
             break;
         L.split <<= 1;
