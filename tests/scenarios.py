@@ -175,7 +175,7 @@ def _sampled_force_check(m, x, v, smp, prec):
     s.set_state(a=a)
     got = [q.cpu().numpy() for q in s.force(smp)]
     ref = oracle.force(m, x, v, a, 1e-4, smp)
-    del s
+    s.close()
     return got, ref
 
 
@@ -234,6 +234,7 @@ def plummer1m(t_end=0.125, n=1 << 20):
                      "n_act_log2_hist": st["hist"][:24],
                      "groups": _hist_groups(st["hist"])}
         _log(f"plummer1m {name}: {json.dumps(res[name])[:300]}")
+        s.close()
         del s
         torch.cuda.empty_cache()
     return res
@@ -283,6 +284,7 @@ def bh64k(n=65536, t_end=0.125):
                      "profiled_wall_s": wall2,
                      "phase_ms": {k: q[0] for k, q in prof.items() if k != "pairs"}}
         _log(f"bh64k {name}: {json.dumps(res[name])[:300]}")
+        s.close()
         del s
         torch.cuda.empty_cache()
     return res
@@ -567,7 +569,7 @@ def _close_systems():
     from paper_1207_2367_amd import System
     gc.collect()
     for o in gc.get_objects():
-        if isinstance(o, System):
+        if type(o) is System:   # (isinstance would touch deprecated torch objects)
             o.close()
     torch.cuda.synchronize()
 
