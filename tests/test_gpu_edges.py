@@ -134,3 +134,28 @@ def test_force_8m_sources_sampled(big, prec):
         check_force(FORCE_TOL[prec], force(s, idx), ref, S)
     del s
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+def test_bench_active_set_8m_sampled(big, prec):
+    """The benchmark's evaluation: 65,536 active particles (seed 5006)
+    against the 2^23 sources, in the launch shape the library picks for it
+    (its rule splits such long source ranges past the usual lane cap), 16 of
+    the active particles against the oracle one by one."""
+    from paper_1207_2367_amd import System
+    m, x, v, a = big[:4]
+    n = m.shape[0]
+    idx = ics.active_subset(n, 65536, 5006)
+    pos = np.sort(np.random.default_rng(7).choice(idx.size, 16, replace=False))
+    ref = oracle.force(m, x, v, a, EPS, idx[pos])
+    S = term_sums(m, x, v, a, EPS, idx[pos])
+    s = System(m, x, v, EPS, precision=prec, skip_startup=True)
+    s.set_state(x=x, v=v, a=a, t=np.zeros(n), dt=np.full(n, DMAX))
+    shape = s.get_launch(idx.size)
+    log_case(test="bench_active_8m", prec=prec, n=n, n_act=idx.size, launch=shape)
+    assert shape[2] > 16   # past the 2^19-lane cap: every split keeps >= 2^17 sources
+    got = [cpu(q) for q in force(s, idx)]
+    check_force(FORCE_TOL[prec], [g[pos] for g in got], ref, S)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
