@@ -326,7 +326,11 @@ Launch pick_launch(const Ctx &c, int64_t n_act, int64_t n_src)
 // a shorter partly empty last round.  Measured at 65,536 active x 8,388,608
 // sources: split 16 / 32 / 64 / 128 / 256 -> 946 / 935 / 930 / 927 / 925 ms,
 // but 3.4 / 4.5 / 6.8 / 11.2 / 20.2 GB fetched (shorter walks, started at
-// staggered times, share the L2 less); 2^17 stops at 64.
+// staggered times, share the L2 less); 2^17 stops at 64.  For the same
+// reason a grid of at most 4096 workgroups (about five rounds of the 768
+// resident ones) is split further while every split keeps 2^15 sources:
+// 131,072 active x 2^20 sources 241 -> 238 ms (split 8 -> 16), 65,536 x 2^21
+// 243 -> 240 ms (16 -> 32), measured.
 Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
 {
     Launch L;
@@ -338,10 +342,15 @@ Launch rule_launch(int64_t n_act, int64_t n_src, int64_t part_cap, int prec)
     L.ipt = prec != NBODY_PREC_FP32PAIR && L.lpi <= 4 && n_act * L.lpi >= (int64_t(1) << 15) ? 2 : 1;
     const int64_t nt = 64 * L.waves;
     const int64_t max_lanes = int64_t(1) << 19, long_split = int64_t(1) << 17;
+    const int64_t few_wgs = 4096, mid_split = int64_t(1) << 15;
+    const int64_t n_ib = (n_act + iblock_size(L) - 1) / iblock_size(L);
     for (;;) {
         const int64_t b2 = (int64_t)L.split * 2, per_split = n_src / b2;
-        if (per_split < 2 * nt || b2 * n_act > part_cap || b2 > 65535 ||   // grid y limit
-            (n_act * L.lpi / L.ipt * b2 > max_lanes && per_split < long_split))
+        if (per_split < 2 * nt || b2 * n_act > part_cap || b2 > 65535)   // grid y limit
+            break;
+        const bool lanes_ok = n_act * L.lpi / L.ipt * b2 <= max_lanes;
+        const bool few = n_ib * b2 <= few_wgs && per_split >= mid_split;
+        if (!lanes_ok && per_split < long_split && !few)
             break;
         L.split <<= 1;
     }
